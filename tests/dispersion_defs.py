@@ -1,0 +1,83 @@
+"""Dispersion functions D(x, k, omega) of the test media, written directly from
+each medium's definition in numpy so that they accept complex arguments.
+
+Used only by tests: complex-step differentiation of these functions gives the
+partial derivatives of D to machine precision (Squire & Trapp, SIAM Review 40
+(1998)), which pins the hand-derived ray right-hand sides of the oracle
+(ray equations, eqs. 2-3: dx/dt = -D_k/D_w, dk/dt = D_x/D_w).
+"""
+import numpy as np
+
+from paper_2508_15967_amd import workloads as W
+
+
+def _bspline_w(u):
+    return [(1 - u) ** 3 / 6, (3 * u ** 3 - 6 * u ** 2 + 4) / 6,
+            (-3 * u ** 3 + 3 * u ** 2 + 3 * u + 1) / 6, u ** 3 / 6]
+
+
+def N_of(med, x):
+    """N(x) (refractive index squared) for isotropic media; x has shape (dim, n)."""
+    p = med.p
+    if med.kind == W.HOMOG:
+        return np.full(x.shape[1:], p[0], dtype=x.dtype)
+    if med.kind == W.LINEARN:
+        return p[0] + sum(p[1 + i] * x[i] for i in range(x.shape[0]))
+    if med.kind == W.LENS2D:
+        n = 1 + p[0] * np.exp(-(x * x).sum(0) / p[1])
+        return n * n
+    if med.kind in (W.STRAT3D, W.BUMPS3D):
+        zeta = (x[2] - p[1]) / p[2]
+        N = 1 - p[0] * np.exp(1 - zeta - np.exp(-zeta))
+        if med.kind == W.BUMPS3D:
+            for b in range(len(med.amps)):
+                c = med.centers[b][:, None]
+                N = N + med.amps[b] * np.exp(-((x - c) ** 2).sum(0) / med.widths[b] ** 2)
+        return N
+    if med.kind == W.SPLINE2D:
+        nx, ny = med.coef.shape
+        h = [(med.hi[0] - med.lo[0]) / (nx - 3), (med.hi[1] - med.lo[1]) / (ny - 3)]
+        s = [(x[i] - med.lo[i]) / h[i] + 1 for i in range(2)]
+        m = [np.clip(np.floor(np.real(s[i])), 1, (nx, ny)[i] - 3).astype(int) for i in range(2)]
+        wx, wy = _bspline_w(s[0] - m[0]), _bspline_w(s[1] - m[1])
+        out = 0
+        for a in range(4):
+            for b in range(4):
+                out = out + med.coef[m[0] - 1 + a, m[1] - 1 + b] * wx[a] * wy[b]
+        return out
+    raise ValueError(med.kind)
+
+
+def D_of(med, x, k, w):
+    """D for every medium kind; arrays (dim, n), w shape (n,)."""
+    if med.kind == W.ANISO3D:
+        D = (k * k).sum(0) - w * w
+        for b in range(len(med.scales)):
+            m6 = med.mats[b]
+            M = np.array([[m6[0], m6[1], m6[2]], [m6[1], m6[3], m6[4]], [m6[2], m6[4], m6[5]]])
+            g = np.exp(-((x - med.centers[b][:, None]) ** 2).sum(0) / med.widths[b] ** 2)
+            q = np.einsum("in,ij,jn->n", k, M, k)
+            D = D + med.scales[b] * g * q
+        return D
+    if med.kind == W.OLINEAR:
+        p = med.p
+        return (k * k).sum(0) - w * w + (p[0] + sum(p[1 + i] * x[i] for i in range(x.shape[0])))
+    return (k * k).sum(0) - w * w * N_of(med, x)
+
+
+def rhs_complex_step(med, y, w, h=1e-30):
+    """Ray right-hand side from complex-step partials of D."""
+    d = y.shape[0] // 2
+    n = y.shape[1]
+    yc = y.astype(np.complex128)
+    wc = np.asarray(w, dtype=np.complex128) * np.ones(n)
+    grads = np.zeros((2 * d, n))
+    for i in range(2 * d):
+        e = yc.copy()
+        e[i] += 1j * h
+        grads[i] = np.imag(D_of(med, e[:d], e[d:], wc)) / h
+    Dw = np.imag(D_of(med, yc[:d], yc[d:], wc + 1j * h)) / h
+    f = np.empty((2 * d, n))
+    f[:d] = -grads[d:] / Dw
+    f[d:] = grads[:d] / Dw
+    return f
