@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 ray-steps/s of the compiled-graph ray tracer on one MI355X.
+
+One benchmark step = one full trace of the workload (every ray advanced by
+every step of its integrator) with inputs resident in HBM.  Default workload:
+the 3-D stratified layer, 1,048,576 rays x 10,000 RK4 steps, every 100th
+state stored (101 snapshots, 5.08 GB).  Other workloads (--config 1..5) are
+available for separate runs; 4 and 5 add the adjoint pass (fwd+adj).
+
+Printed: one JSON line with the persistent-kernel throughput, the plain
+one-launch-per-step comparator, a roofline entry for the dominant kernel
+(FP64 vector ALU bound, flops counted from the compiled graph) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="2")
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed plain-form traces")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0 = auto)")
+    ap.add_argument("--traffic", default="", help="JSON file with measured HBM bytes per launch")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+    from paper_2508_15967_amd import media, raygraph as rgb, workloads as W
+
+    w = W.make(args.config)
+    adjoint = args.config in ("4", "5")
+    dev = torch.device("cuda:0")
+    g, D, params = media.build(w.medium)
+    t0 = time.time()
+    prog = g.compile(D, want_adjoint=adjoint)
+    compile_s = time.time() - t0
+    info = prog.info()
+    n, d, ny = w.n, w.dim, 2 * w.dim
+    x0 = torch.from_numpy(w.x0).to(dev)
+    k0 = torch.from_numpy(w.k0).to(dev)
+    om = torch.from_numpy(w.omega).to(dev)
+    pt = [torch.from_numpy(p).to(dev) for p in params]
+    kw = dict(integrator=w.integrator, dt=w.dt, n_steps=w.n_steps, h0=w.h0, rtol=w.rtol,
+              atol=w.atol, hmin=w.hmin)
+    if w.budget is not None:
+        kw["budget"] = torch.from_numpy(w.budget.astype(np.int32)).to(dev)
+    if w.box_lo is not None:
+        kw["box"] = (list(w.box_lo), list(w.box_hi))
+    outs = {"x_out": torch.empty((d, n), dtype=torch.float64, device=dev),
+            "k_out": torch.empty((d, n), dtype=torch.float64, device=dev),
+            "t_out": torch.empty(n, dtype=torch.float64, device=dev),
+            "status_out": torch.empty(n, dtype=torch.int32, device=dev),
+            "steps_out": torch.empty(n, dtype=torch.int32, device=dev)}
+    if w.store_every > 0:
+        ns = w.n_steps // w.store_every + 1
+        outs["traj"] = torch.empty((ns, ny, n), dtype=torch.float64, device=dev)
+        kw["store_every"] = w.store_every
+    ckpt = None
+    if adjoint:
+        nc = (w.n_steps + w.ckpt_every - 1) // w.ckpt_every
+        ckpt = torch.empty((nc, ny + 1, n), dtype=torch.float64, device=dev)
+        kw["checkpoint_every"] = w.ckpt_every
+        kw["checkpoints"] = ckpt
+    stream = torch.cuda.current_stream()
+
+    def make(mode):
+        return prog.make_desc(x0, k0, om, pt, mode=mode, use_hipgraph=True, **kw, **outs)
+
+    desc = make(rgb.PERSISTENT)
+    adj = {}
+    if adjoint:
+        tx = torch.from_numpy(w.targets).to(dev)
+        adj = {"lx": torch.empty((d, n), dtype=torch.float64, device=dev),
+               "gx0": torch.empty((d, n), dtype=torch.float64, device=dev),
+               "gk0": torch.empty((d, n), dtype=torch.float64, device=dev),
+               "gp": [torch.empty_like(p) for p in pt], "tx": tx}
+
+    def fwd():
+        prog.trace_desc(desc, stream)
+
+    def bwd():
+        # dL/dx_end of L = sum |x_end - target|^2
+        torch.mul(outs["x_out"] - adj["tx"], 2.0, out=adj["lx"])
+        prog.adjoint_desc(desc, adj["lx"], None, adj["gx0"], adj["gk0"], adj["gp"], stream)
+
+    # warmup (includes autotuning and hipGraph capture on the first call)
+    t0 = time.time()
+    for _ in range(max(args.warmup, 1)):
+        fwd()
+        if adjoint:
+            bwd()
+    torch.cuda.synchronize()
+    warm_s = time.time() - t0
+    launch = prog.last_launch()
+
+    # timed region
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    evb = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)] if adjoint else []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        fwd()
+        ev[i][1].record(stream)
+        if adjoint:
+            evb[i][0].record(stream)
+            bwd()
+            evb[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evb])) if adjoint else 0.0
+
+    st = outs["status_out"].cpu().numpy()
+    steps = outs["steps_out"].cpu().numpy().astype(np.int64)
+    ray_steps = int(steps.sum())
+    ms_per_step = wall * 1e3 / args.steps
+    value = ray_steps * args.steps / wall
+
+    if w.integrator == W.RK4:
+        flops_alg = info["rk4_step_flops_alg"] * ray_steps
+        flops_iss = info["rk4_step_flops_issued"] * ray_steps
+    else:
+        # attempts are not returned per ray; accepted steps x attempt cost is
+        # a lower bound of the work done
+        flops_alg = info["dopri_attempt_flops_alg"] * ray_steps
+        flops_iss = info["dopri_attempt_flops_issued"] * ray_steps
+    kernel_ms = fwd_ms
+    if adjoint:
+        flops_alg_adj = info["adj_step_flops_alg"] * ray_steps
+        flops_iss_adj = info["adj_step_flops_issued"] * ray_steps
+    achieved = flops_alg / (kernel_ms * 1e-3) / 1e12
+    achieved_iss = flops_iss / (kernel_ms * 1e-3) / 1e12
+
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        tj = json.load(open(args.traffic))
+        if tj.get("source_hash") == info["source_hash"] and tj.get("config") == args.config:
+            traffic = tj.get("bytes_per_launch")
+
+    result = {
+        "metric": "FP64 ray-steps/s (persistent fused RK4, one launch per trace)",
+        "value": value, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n_rays": n, "integrator": "RK4" if w.integrator == W.RK4 else "DOPRI54",
+                   "n_steps": w.n_steps, "dt": w.dt, "store_every": w.store_every,
+                   "ray_steps_per_trace": ray_steps, "adjoint": adjoint},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "rg_rk4_r%d" % launch["rays_per_lane"] if w.integrator == W.RK4 else "rg_dopri_persistent",
+                     "kernel_ms": kernel_ms, "flops_per_ray_step_alg": flops_alg / max(ray_steps, 1),
+                     "achieved_issued": achieved_iss, "frac_issued": achieved_iss / PEAK_FP64_TFLOPS},
+        "launch": launch, "compile_s": compile_s, "warmup_s": warm_s,
+        "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+    }
+    if adjoint:
+        tot_ms = fwd_ms + bwd_ms
+        result["metric"] = "FP64 ray-steps/s fwd+adjoint (persistent RK4 + checkpointed discrete adjoint)"
+        result["value"] = value
+        result["fwd"] = {"ray_steps_per_s": ray_steps / (fwd_ms * 1e-3), "ms": fwd_ms}
+        result["fwd_adj"] = {"ray_steps_per_s": ray_steps / (tot_ms * 1e-3), "ms": tot_ms,
+                             "adj_ms": bwd_ms,
+                             "tflops_alg": (flops_alg + flops_alg_adj) / (tot_ms * 1e-3) / 1e12,
+                             "tflops_issued": (flops_iss + flops_iss_adj) / (tot_ms * 1e-3) / 1e12}
+        result["fwd_adj"]["frac_alg"] = result["fwd_adj"]["tflops_alg"] / PEAK_FP64_TFLOPS
+        result["fwd_adj"]["frac_issued"] = result["fwd_adj"]["tflops_issued"] / PEAK_FP64_TFLOPS
+
+    # plain one-launch-per-step comparator on the same GPU and inputs
+    if not args.no_plain:
+        pdesc = prog.make_desc(x0, k0, om, pt, mode=rgb.PLAIN, use_hipgraph=False, **kw, **outs)
+        prog.trace_desc(pdesc, stream)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            prog.trace_desc(pdesc, stream)
+        torch.cuda.synchronize()
+        pw = (time.perf_counter() - t0) / args.plain_steps
+        psteps = int(outs["steps_out"].cpu().numpy().astype(np.int64).sum())
+        result["plain"] = {"value": psteps / pw, "ms_per_trace": pw * 1e3,
+                           "launches_per_trace": w.n_steps + 2 if w.integrator == W.RK4 else None}
+        result["speedup_vs_plain"] = (ray_steps / (ms_per_step * 1e-3)) / (psteps / pw)
+
+    # CPU oracle on a bounded sample of the same workload
+    if not args.no_cpu:
+        from oracle import pyoracle
+        pyoracle.build(force=False)
+        cores = pyoracle.threads()
+        m = args.cpu_rays or {"1": 1024, "2": 16 * cores * 64, "3": 8 * cores * 64,
+                              "4": 2 * cores * 64, "5": cores * 8}.get(args.config, 4096)
+        ws = w.subset(min(m, w.n))
+        t0 = time.perf_counter()
+        ro = pyoracle.trace(ws)
+        if adjoint:
+            lam = np.concatenate([2 * (ro["x"] - ws.targets), np.zeros_like(ro["k"])])
+            pyoracle.adjoint(ws, lam)
+        cs = time.perf_counter() - t0
+        crs = int(ro["steps"].astype(np.int64).sum())
+        result["cpu_baseline"] = {"value": crs / cs, "unit": "ray-steps/s" + (" (fwd+adj)" if adjoint else ""),
+                                  "cores": cores, "kind": "oracle",
+                                  "sample": f"first {ws.n} rays of {w.name}, all steps, {cs:.1f} s"}
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,63 @@
+// Emission of straight-line HIP device functions from the expression graph.
+//
+// Paper, "JIT" subsection: the kernel body is produced by a recursive
+// traversal of the graph that writes one line per node into its own
+// register variable, skipping sub-graphs already emitted, with memory loaded
+// once at the start and stored once at the end.  Here the traversal is the
+// index order of the hash-consed arena (already topological), a multiply
+// used only by one add/subtract becomes an explicit fma, and the nodes of a
+// B-spline that share a cell share one gather of the 16 coefficients.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "graph.hpp"
+
+namespace rg {
+
+struct Flops {
+    double alg = 0.0;     // add/sub/mul/div/sqrt/exp/... = 1, fma = 2
+    double issued = 0.0;  // FP64 add/mul/fma flops of the gfx950 expansion
+    uint32_t ops = 0;     // emitted operations
+    void add(const Flops &o) { alg += o.alg; issued += o.issued; ops += o.ops; }
+};
+
+// Issued FP64 flops of one operation's instruction expansion on gfx950
+// (fma counted as 2, add/mul as 1; compares, selects, integer and exponent
+// manipulation count 0).
+struct IssuedWeights {
+    double div, exp, log, sqrt, sincos;
+};
+const IssuedWeights &issued_weights();
+
+struct Output {
+    uint32_t node;
+    std::string lhs;   // e.g. "f[0]"
+    bool accumulate;   // "+=" instead of "="
+};
+
+// A spline coefficient table whose gradient is scattered: for every spline
+// node of the table reachable from the function, `seed` gives d(out)/d(node)
+// (a node of the same graph).
+struct SplineSeed {
+    uint32_t spline_node;
+    uint32_t seed;
+};
+
+struct FunctionSpec {
+    std::string signature;  // full function head, up to and including "{"
+    std::vector<Output> outputs;
+    std::vector<SplineSeed> spline_seeds;  // VJP only
+    bool returns_value = false;            // single output via "return"
+};
+
+// Emit a function.  `tables` maps a spline-definition's parameter to a table
+// slot used by the RG_SPL_TAB(slot) accessor; `grad_tables` is the same for
+// the gradient accumulator.
+std::string emit_function(const Graph &g, const FunctionSpec &spec,
+                          const std::vector<int> &param_table_slot, Flops *flops);
+
+std::string hex_double(double v);
+
+}  // namespace rg

@@ -1,0 +1,381 @@
+// Expression graph construction, reduction, differentiation and evaluation.
+// Paper, "Graph" subsection and the worked example that follows Listing 1.
+#include "graph.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <sstream>
+#include <stdexcept>
+
+namespace rg {
+
+static uint64_t dbits(double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, 8);
+    return b;
+}
+
+size_t Graph::KeyHash::operator()(const Key &k) const {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    };
+    mix((uint64_t)(uint32_t)k.op);
+    mix((uint64_t)(uint32_t)k.aux);
+    mix(k.a);
+    mix(k.b);
+    mix(k.bits);
+    return (size_t)h;
+}
+
+Graph::Graph(uint32_t dim) : dim_(dim) {
+    nodes_.reserve(1024);
+    // pre-declare the kernel inputs: x[dim], k[dim], omega, t
+    for (uint32_t i = 0; i < dim; i++) var(VK_X, i);
+    for (uint32_t i = 0; i < dim; i++) var(VK_K, i);
+    var(VK_OMEGA, 0);
+    var(VK_T, 0);
+}
+
+uint32_t Graph::intern(int32_t op, int32_t aux, uint32_t a, uint32_t b, double val) {
+    // +0.0 and -0.0 are one constant for hashing purposes only if equal bits;
+    // keep them distinct (they differ under division).
+    Key key{op, aux, a, b, dbits(val)};
+    auto it = cache_.find(key);
+    if (it != cache_.end()) return it->second;
+    uint32_t id = (uint32_t)nodes_.size();
+    nodes_.push_back(Node{op, aux, a, b, val});
+    cache_.emplace(key, id);
+    return id;
+}
+
+double Graph::fold(int32_t op, double a, double b, int32_t aux) const {
+    switch (op) {
+    case ADD: return a + b;
+    case SUB: return a - b;
+    case MUL: return a * b;
+    case DIV: return a / b;
+    case NEG: return -a;
+    case EXP: return std::exp(a);
+    case LOG: return std::log(a);
+    case SQRT: return std::sqrt(a);
+    case SIN: return std::sin(a);
+    case COS: return std::cos(a);
+    case POWI: {
+        double r = 1.0, base = a;
+        int n = aux < 0 ? -aux : aux;
+        for (int i = 0; i < n; i++) r *= base;
+        return aux < 0 ? 1.0 / r : r;
+    }
+    }
+    return NAN;
+}
+
+uint32_t Graph::constant(double v) { return intern(CONST, 0, NONE, NONE, v); }
+
+uint32_t Graph::var(int32_t kind, uint32_t i) { return intern(VAR, kind * 8 + (int32_t)i, NONE, NONE, 0.0); }
+
+uint32_t Graph::param_elem(uint32_t param, uint32_t idx) {
+    if (param >= params_.size() || idx >= params_[param].len)
+        throw std::invalid_argument("parameter element out of range");
+    return intern(PARAM, (int32_t)param, NONE, NONE, (double)idx);
+}
+
+uint32_t Graph::declare_param(const std::string &name, uint32_t len) {
+    params_.push_back(ParamDef{name, len});
+    return (uint32_t)params_.size() - 1;
+}
+
+uint32_t Graph::declare_spline(const SplineDef &d) {
+    for (size_t i = 0; i < splines_.size(); i++) {
+        const SplineDef &s = splines_[i];
+        if (s.param == d.param && s.nx == d.nx && s.ny == d.ny && s.lo[0] == d.lo[0] &&
+            s.lo[1] == d.lo[1] && s.hi[0] == d.hi[0] && s.hi[1] == d.hi[1])
+            return (uint32_t)i;
+    }
+    splines_.push_back(d);
+    return (uint32_t)splines_.size() - 1;
+}
+
+// ------------------------------------------------------------ arithmetic ---
+
+uint32_t Graph::add(uint32_t a, uint32_t b) {
+    if (is_const(a) && is_const(b)) return constant(nodes_[a].val + nodes_[b].val);
+    if (is_const(a, 0.0)) return b;
+    if (is_const(b, 0.0)) return a;
+    const Node &na = nodes_[a], &nb = nodes_[b];
+    if (nb.op == NEG) return sub(a, nb.a);          // a + (-b) -> a - b
+    if (na.op == NEG) return sub(b, na.a);          // (-a) + b -> b - a
+    if (a == b) return mul(constant(2.0), a);       // x + x -> 2 x
+    // canonical operand order: constants first, then by index
+    if (is_const(b) || (!is_const(a) && b < a)) std::swap(a, b);
+    return intern(ADD, 0, a, b, 0.0);
+}
+
+uint32_t Graph::sub(uint32_t a, uint32_t b) {
+    if (is_const(a) && is_const(b)) return constant(nodes_[a].val - nodes_[b].val);
+    if (is_const(b, 0.0)) return a;
+    if (is_const(a, 0.0)) return neg(b);
+    if (a == b) return constant(0.0);
+    const Node &nb = nodes_[b];
+    if (nb.op == NEG) return add(a, nb.a);          // a - (-b) -> a + b
+    if (nodes_[a].op == NEG) return neg(add(nodes_[a].a, b));  // -a - b -> -(a + b)
+    return intern(SUB, 0, a, b, 0.0);
+}
+
+uint32_t Graph::mul(uint32_t a, uint32_t b) {
+    if (is_const(b) && !is_const(a)) std::swap(a, b);
+    if (is_const(a) && is_const(b)) return constant(nodes_[a].val * nodes_[b].val);
+    if (is_const(a, 0.0) || is_const(b, 0.0)) return constant(0.0);  // x*0 -> 0 (as the paper)
+    if (is_const(a, 1.0)) return b;
+    if (is_const(a, -1.0)) return neg(b);
+    const Node &na = nodes_[a], &nb = nodes_[b];
+    if (na.op == NEG && nb.op == NEG) return mul(na.a, nb.a);
+    if (na.op == NEG) return neg(mul(na.a, b));
+    if (nb.op == NEG) return neg(mul(a, nb.a));
+    // c1 * (c2 * x) -> (c1 c2) * x
+    if (is_const(a) && nb.op == MUL && is_const(nb.a)) return mul(constant(na.val * nodes_[nb.a].val), nb.b);
+    if (!is_const(a) && b < a) std::swap(a, b);
+    return intern(MUL, 0, a, b, 0.0);
+}
+
+uint32_t Graph::div(uint32_t a, uint32_t b) {
+    if (is_const(a) && is_const(b)) return constant(nodes_[a].val / nodes_[b].val);
+    if (is_const(b, 1.0)) return a;
+    if (is_const(b, -1.0)) return neg(a);
+    if (is_const(a, 0.0)) return constant(0.0);
+    const Node &na = nodes_[a], &nb = nodes_[b];
+    if (na.op == NEG) return neg(div(na.a, b));
+    if (nb.op == NEG) return neg(div(a, nb.a));
+    if (is_const(b)) {
+        // division by a power of two is an exact multiplication
+        int e;
+        double m = std::frexp(nb.val, &e);
+        if (m == 0.5 || m == -0.5) return mul(constant(1.0 / nb.val), a);
+    }
+    return intern(DIV, 0, a, b, 0.0);
+}
+
+uint32_t Graph::neg(uint32_t a) {
+    if (is_const(a)) return constant(-nodes_[a].val);
+    const Node &na = nodes_[a];
+    if (na.op == NEG) return na.a;
+    if (na.op == MUL && is_const(na.a)) return mul(constant(-nodes_[na.a].val), na.b);
+    if (na.op == SUB) return sub(na.b, na.a);
+    return intern(NEG, 0, a, NONE, 0.0);
+}
+
+uint32_t Graph::unary(int32_t op, uint32_t a) {
+    if (op != EXP && op != LOG && op != SQRT && op != SIN && op != COS)
+        throw std::invalid_argument("bad unary op");
+    if (is_const(a)) return constant(fold(op, nodes_[a].val, 0.0, 0));
+    return intern(op, 0, a, NONE, 0.0);
+}
+
+uint32_t Graph::powi(uint32_t a, int32_t n) {
+    if (n == 0) return constant(1.0);
+    if (n == 1) return a;
+    if (is_const(a)) return constant(fold(POWI, nodes_[a].val, 0.0, n));
+    if (n == -1) return div(constant(1.0), a);
+    return intern(POWI, n, a, NONE, 0.0);
+}
+
+uint32_t Graph::spline(uint32_t def, int32_t du, int32_t dv, uint32_t u, uint32_t v) {
+    if (def >= splines_.size()) throw std::invalid_argument("bad spline definition");
+    if (du > 3 || dv > 3) return constant(0.0);  // cubic: 4th derivative vanishes
+    return intern(SPLINE, du * 4 + dv, u, v, (double)def);
+}
+
+// -------------------------------------------------------------------- df ---
+
+std::vector<uint32_t> Graph::reachable(const std::vector<uint32_t> &roots) const {
+    std::vector<char> mark(nodes_.size(), 0);
+    std::vector<uint32_t> stack(roots.begin(), roots.end());
+    while (!stack.empty()) {
+        uint32_t n = stack.back();
+        stack.pop_back();
+        if (n == NONE || mark[n]) continue;
+        mark[n] = 1;
+        const Node &nd = nodes_[n];
+        if (nd.a != NONE) stack.push_back(nd.a);
+        if (nd.b != NONE) stack.push_back(nd.b);
+    }
+    std::vector<uint32_t> out;
+    for (uint32_t i = 0; i < mark.size(); i++)
+        if (mark[i]) out.push_back(i);
+    return out;
+}
+
+uint32_t Graph::df(uint32_t f, uint32_t wrt) {
+    // Forward sweep over the nodes f depends on (indices are topological);
+    // d[n] = d node_n / d wrt, built with the same reducing factories.
+    std::vector<uint32_t> order = reachable({f});
+    std::unordered_map<uint32_t, uint32_t> d;
+    d.reserve(order.size() * 2);
+    const uint32_t zero = constant(0.0), one = constant(1.0);
+    for (uint32_t n : order) {
+        if (n == wrt) { d[n] = one; continue; }
+        const Node nd = nodes_[n];  // copy: factories may grow nodes_
+        uint32_t da = nd.a != NONE ? d[nd.a] : zero;
+        uint32_t db = nd.b != NONE ? d[nd.b] : zero;
+        uint32_t r = zero;
+        switch (nd.op) {
+        case CONST: case VAR: case PARAM:
+            r = zero;
+            break;
+        case ADD: r = add(da, db); break;
+        case SUB: r = sub(da, db); break;
+        case MUL: r = add(mul(da, nd.b), mul(nd.a, db)); break;
+        case DIV:
+            // (a/b)' = (a' - (a/b) b') / b;  (1/b)' = -(1/b)^2 b' needs no division
+            if (is_const(db, 0.0)) r = div(da, nd.b);
+            else if (is_const(nd.a, 1.0)) r = neg(mul(mul(n, n), db));
+            else r = div(sub(da, mul(n, db)), nd.b);
+            break;
+        case NEG: r = neg(da); break;
+        case EXP: r = mul(n, da); break;
+        case LOG: r = div(da, nd.a); break;
+        case SQRT: r = div(mul(constant(0.5), da), n); break;
+        case SIN: r = mul(unary(COS, nd.a), da); break;
+        case COS: r = neg(mul(unary(SIN, nd.a), da)); break;
+        case POWI:
+            r = mul(mul(constant((double)nd.aux), powi(nd.a, nd.aux - 1)), da);
+            break;
+        case SPLINE: {
+            int du = nd.aux / 4, dv = nd.aux % 4;
+            uint32_t def = (uint32_t)nd.val;
+            r = add(mul(spline(def, du + 1, dv, nd.a, nd.b), da),
+                    mul(spline(def, du, dv + 1, nd.a, nd.b), db));
+            break;
+        }
+        }
+        d[n] = r;
+    }
+    return d[f];
+}
+
+// -------------------------------------------------------------- evaluate ---
+
+void bspline_weights(int order, double u, double w[4]) {
+    double v = 1.0 - u;
+    switch (order) {
+    case 0:
+        w[0] = v * v * v / 6.0;
+        w[1] = (3.0 * u * u * u - 6.0 * u * u + 4.0) / 6.0;
+        w[2] = (-3.0 * u * u * u + 3.0 * u * u + 3.0 * u + 1.0) / 6.0;
+        w[3] = u * u * u / 6.0;
+        break;
+    case 1:
+        w[0] = -v * v / 2.0;
+        w[1] = (3.0 * u * u - 4.0 * u) / 2.0;
+        w[2] = (-3.0 * u * u + 2.0 * u + 1.0) / 2.0;
+        w[3] = u * u / 2.0;
+        break;
+    case 2:
+        w[0] = v; w[1] = 3.0 * u - 2.0; w[2] = 1.0 - 3.0 * u; w[3] = u;
+        break;
+    default:
+        w[0] = -1.0; w[1] = 3.0; w[2] = -3.0; w[3] = 1.0;
+        break;
+    }
+}
+
+void bspline_cell(double x, double lo, double hi, uint32_t n, int *m, double *u, double *invh) {
+    *invh = (double)(n - 3) / (hi - lo);
+    double s = (x - lo) * *invh + 1.0;
+    double fm = std::floor(s);
+    fm = std::min(std::max(fm, 1.0), (double)(n - 3));
+    *m = (int)fm;
+    *u = s - fm;
+}
+
+double Graph::eval(uint32_t f, const double *x, const double *k, double omega, double t,
+                   const double *const *params, const double *seeds) const {
+    std::vector<uint32_t> order = reachable({f});
+    std::unordered_map<uint32_t, double> v;
+    v.reserve(order.size() * 2);
+    for (uint32_t n : order) {
+        const Node &nd = nodes_[n];
+        double r = 0.0;
+        switch (nd.op) {
+        case CONST: r = nd.val; break;
+        case VAR: {
+            int kind = nd.aux / 8, i = nd.aux % 8;
+            r = kind == VK_X ? x[i] : kind == VK_K ? k[i] : kind == VK_OMEGA ? omega
+                : kind == VK_T ? t : (seeds ? seeds[i] : 0.0);
+            break;
+        }
+        case PARAM: {
+            const double *p = params ? params[nd.aux] : nullptr;
+            if (!p) throw std::invalid_argument("parameter value missing");
+            r = p[(size_t)nd.val];
+            break;
+        }
+        case SPLINE: {
+            const SplineDef &s = splines_[(size_t)nd.val];
+            const double *c = params ? params[s.param] : nullptr;
+            if (!c) throw std::invalid_argument("spline coefficients missing");
+            int mx, my;
+            double ux, uy, ihx, ihy, wx[4], wy[4];
+            bspline_cell(v[nd.a], s.lo[0], s.hi[0], s.nx, &mx, &ux, &ihx);
+            bspline_cell(v[nd.b], s.lo[1], s.hi[1], s.ny, &my, &uy, &ihy);
+            int du = nd.aux / 4, dv = nd.aux % 4;
+            bspline_weights(du, ux, wx);
+            bspline_weights(dv, uy, wy);
+            double acc = 0.0;
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++)
+                    acc += c[(size_t)(mx - 1 + a) * s.ny + (my - 1 + b)] * wx[a] * wy[b];
+            for (int i = 0; i < du; i++) acc *= ihx;
+            for (int i = 0; i < dv; i++) acc *= ihy;
+            r = acc;
+            break;
+        }
+        case POWI: r = fold(POWI, v[nd.a], 0.0, nd.aux); break;
+        default:
+            r = fold(nd.op, v[nd.a], nd.b != NONE ? v[nd.b] : 0.0, nd.aux);
+        }
+        v[n] = r;
+    }
+    return v[f];
+}
+
+// ------------------------------------------------------------- rendering ---
+
+std::string Graph::to_string(uint32_t n) const {
+    const Node &nd = nodes_[n];
+    std::ostringstream os;
+    os.precision(17);
+    auto s = [this](uint32_t m) { return to_string(m); };
+    static const char *vn[] = {"x", "k", "omega", "t", "v"};
+    switch (nd.op) {
+    case CONST: os << nd.val; break;
+    case VAR: {
+        int kind = nd.aux / 8, i = nd.aux % 8;
+        os << vn[kind];
+        if (kind == VK_X || kind == VK_K || kind == VK_SEED) os << i;
+        break;
+    }
+    case PARAM: os << params_[nd.aux].name << "[" << (size_t)nd.val << "]"; break;
+    case ADD: os << "(" << s(nd.a) << " + " << s(nd.b) << ")"; break;
+    case SUB: os << "(" << s(nd.a) << " - " << s(nd.b) << ")"; break;
+    case MUL: os << "(" << s(nd.a) << "*" << s(nd.b) << ")"; break;
+    case DIV: os << "(" << s(nd.a) << "/" << s(nd.b) << ")"; break;
+    case NEG: os << "(-" << s(nd.a) << ")"; break;
+    case EXP: os << "exp(" << s(nd.a) << ")"; break;
+    case LOG: os << "log(" << s(nd.a) << ")"; break;
+    case SQRT: os << "sqrt(" << s(nd.a) << ")"; break;
+    case SIN: os << "sin(" << s(nd.a) << ")"; break;
+    case COS: os << "cos(" << s(nd.a) << ")"; break;
+    case POWI: os << "(" << s(nd.a) << ")^" << nd.aux; break;
+    case SPLINE:
+        os << "spline" << (size_t)nd.val << "_d" << nd.aux / 4 << nd.aux % 4 << "(" << s(nd.a)
+           << ", " << s(nd.b) << ")";
+        break;
+    }
+    return os.str();
+}
+
+}  // namespace rg

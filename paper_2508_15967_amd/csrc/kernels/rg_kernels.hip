@@ -1,0 +1,677 @@
+// Integrator kernels for gfx950 (wave64), FP64.  This text is compiled at
+// run time by hipRTC together with the device functions emitted from the
+// expression graph:
+//   rg_config.h     RG_DIM, RG_NY, table and gradient-slot layout (generated)
+//   rg_prelude.h    B-spline helpers, rg_P
+//   rg_functions.h  rg_rhs, rg_D and (with RG_HAS_VJP) rg_vjp (generated)
+//
+// The paper's kernel takes x, k, t, omega and returns the D residual and
+// the RK4 update of x, k, t, with setter maps feeding outputs back to inputs
+// for the next step ("Impact" and "JIT" sections).  The persistent kernels
+// here keep that loop inside the kernel: each lane holds its ray in
+// registers for all steps and touches HBM only for the initial load,
+// snapshots/checkpoints and the final store.  The "plain" kernels keep the
+// paper's one-launch-per-step structure (state round-trips through HBM) and
+// serve as the comparison baseline.
+#include "rg_kargs.h"
+#include "rg_config.h"
+#include "rg_prelude.h"
+
+#define RG_RAY_OK 0
+#define RG_RAY_EXITED_BOX 1
+#define RG_RAY_BUDGET 2
+#define RG_RAY_NONFINITE 3
+#define RG_RAY_STEP_UNDERFLOW 4
+
+// ---------------------------------------------------------------- tables --
+#if RG_NSPLTAB > 0
+__shared__ double rg_spl_lds[RG_SPL_TOTAL];
+#define RG_SPL_TAB(k) (rg_spl_lds + rg_spl_off[k])
+#endif
+
+// Gradient accumulator for spline coefficient tables (adjoint only): the
+// 16 coefficient gradients of the current cell stay in registers while the
+// ray stays in that cell and are flushed to an LDS copy of the table with
+// atomics when it leaves.
+#if RG_HAS_VJP && RG_NSPLTAB > 0
+__shared__ double rg_spl_grad_lds[RG_SPL_TOTAL];
+struct rg_GA {
+    int cx[RG_NSPLTAB], cy[RG_NSPLTAB];
+    double acc[RG_NSPLTAB][16];
+    __device__ __forceinline__ void init() {
+        for (int k = 0; k < RG_NSPLTAB; k++) { cx[k] = -1; cy[k] = -1; }
+    }
+    __device__ __forceinline__ void flush(int k) {
+        if (cx[k] >= 0) {
+            double *base = rg_spl_grad_lds + rg_spl_off[k] + (cx[k] - 1) * rg_spl_ny[k] + (cy[k] - 1);
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) atomicAdd(base + a * rg_spl_ny[k] + b, acc[k][4 * a + b]);
+        }
+    }
+    __device__ __forceinline__ void add(int k, int x, int y, const double *g) {
+        if (x != cx[k] || y != cy[k]) {
+            flush(k);
+            cx[k] = x;
+            cy[k] = y;
+            for (int i = 0; i < 16; i++) acc[k][i] = g[i];
+        } else {
+            for (int i = 0; i < 16; i++) acc[k][i] += g[i];
+        }
+    }
+};
+#else
+struct rg_GA {
+    __device__ __forceinline__ void init() {}
+    __device__ __forceinline__ void flush(int) {}
+    __device__ __forceinline__ void add(int, int, int, const double *) {}
+};
+#endif
+
+#include "rg_functions.h"
+
+__device__ __forceinline__ void rg_stage_tables(const rg_kargs &a) {
+#if RG_NSPLTAB > 0
+    for (int k = 0; k < RG_NSPLTAB; k++) {
+        const double *src = a.params[rg_spl_param[k]];
+        for (int i = threadIdx.x; i < rg_spl_len[k]; i += blockDim.x) rg_spl_lds[rg_spl_off[k] + i] = src[i];
+    }
+    __syncthreads();
+#endif
+}
+
+__device__ __forceinline__ rg_P rg_params(const rg_kargs &a) {
+    rg_P P;
+    for (int i = 0; i < RG_MAX_PARAMS; i++) P.p[i] = a.params[i];
+    return P;
+}
+
+__device__ __forceinline__ bool rg_finite(const double *y) {
+    bool f = true;
+    for (int i = 0; i < RG_NY; i++) f = f && __builtin_isfinite(y[i]);
+    return f;
+}
+
+__device__ __forceinline__ bool rg_outside(const rg_kargs &a, const double *y) {
+    bool o = false;
+    for (int i = 0; i < RG_DIM; i++) o = o || (y[i] < a.box_lo[i]) || (y[i] > a.box_hi[i]);
+    return o;
+}
+
+// One classic RK4 step (weights 1/6, 1/3, 1/3, 1/6), fused: the stage
+// vectors live in registers and the update accumulates as the stages come.
+__device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t, double dt,
+                                            const rg_P &P, double *yn) {
+    const double h2 = 0.5 * dt, dt6 = dt / 6.0;
+    double K[RG_NY], acc[RG_NY], Y[RG_NY];
+    rg_rhs(y, om, t, P, K);
+    for (int i = 0; i < RG_NY; i++) { acc[i] = K[i]; Y[i] = fma(h2, K[i], y[i]); }
+    rg_rhs(Y, om, t + h2, P, K);
+    for (int i = 0; i < RG_NY; i++) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(h2, K[i], y[i]); }
+    rg_rhs(Y, om, t + h2, P, K);
+    for (int i = 0; i < RG_NY; i++) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
+    rg_rhs(Y, om, t + dt, P, K);
+    for (int i = 0; i < RG_NY; i++) { acc[i] = acc[i] + K[i]; yn[i] = fma(dt6, acc[i], y[i]); }
+}
+
+// ------------------------------------------------------- persistent RK4 --
+// Grid-stride over rays; R rays per lane advanced in lock-step so that the
+// compiler can interleave their independent right-hand sides.
+template <int R>
+__device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
+    rg_stage_tables(a);
+    const rg_P P = rg_params(a);
+    const long long n = a.n;
+    const long long G = (long long)gridDim.x * blockDim.x;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double dt = a.dt;
+    const long long nr = a.n_run;
+    for (long long base = gid; base < nr; base += G * R) {
+        double y[R][RG_NY], t[R], om[R];
+        int st[R], ns[R];
+        long long rid[R];
+        for (int r = 0; r < R; r++) {
+            rid[r] = base + (long long)r * G;
+            const long long q = rid[r] < nr ? rid[r] : base;  // inactive slot re-reads a valid ray
+            for (int i = 0; i < RG_DIM; i++) {
+                y[r][i] = a.x0[i * n + q];
+                y[r][RG_DIM + i] = a.k0[i * n + q];
+            }
+            t[r] = a.t0 ? a.t0[q] : 0.0;
+            om[r] = a.omega[q];
+            st[r] = rid[r] < nr ? RG_RAY_OK : -1;
+            ns[r] = 0;
+        }
+        int snap = 0, snap_cd = a.store_every, ck = 0, ck_cd = 0;
+        if (a.store_every > 0) {
+            for (int r = 0; r < R; r++)
+                if (st[r] >= 0) {
+                    for (int c = 0; c < RG_NY; c++) a.traj[(long long)c * n + rid[r]] = y[r][c];
+                    if (a.traj_D) a.traj_D[rid[r]] = rg_D(y[r], om[r], t[r], P);
+                }
+            snap = 1;
+        }
+        for (int s = 0; s < a.n_steps; s++) {
+            if (a.ckpt_every > 0 && ck_cd == 0) {
+                for (int r = 0; r < R; r++)
+                    if (st[r] >= 0) {
+                        double *cp = a.ckpt + (long long)ck * (RG_NY + 1) * n + rid[r];
+                        for (int c = 0; c < RG_NY; c++) cp[(long long)c * n] = y[r][c];
+                        cp[(long long)RG_NY * n] = t[r];
+                    }
+                ck++;
+                ck_cd = a.ckpt_every;
+            }
+            ck_cd--;
+            double yn[R][RG_NY];
+            for (int r = 0; r < R; r++) rg_rk4_step(y[r], om[r], t[r], dt, P, yn[r]);
+            for (int r = 0; r < R; r++) {
+                const bool fin = rg_finite(yn[r]);
+                const bool live = st[r] == RG_RAY_OK;
+                if (live && fin) {
+                    for (int c = 0; c < RG_NY; c++) y[r][c] = yn[r][c];
+                    t[r] = t[r] + dt;
+                    ns[r]++;
+                    if (a.has_box && rg_outside(a, y[r])) st[r] = RG_RAY_EXITED_BOX;
+                } else if (live) {
+                    st[r] = RG_RAY_NONFINITE;
+                }
+            }
+            if (a.store_every > 0 && --snap_cd == 0) {
+                for (int r = 0; r < R; r++)
+                    if (st[r] >= 0) {
+                        double *tp = a.traj + (long long)snap * RG_NY * n + rid[r];
+                        for (int c = 0; c < RG_NY; c++) tp[(long long)c * n] = y[r][c];
+                        if (a.traj_D) a.traj_D[(long long)snap * n + rid[r]] = rg_D(y[r], om[r], t[r], P);
+                    }
+                snap++;
+                snap_cd = a.store_every;
+            }
+        }
+        for (int r = 0; r < R; r++) {
+            if (st[r] < 0) continue;
+            for (int i = 0; i < RG_DIM; i++) {
+                a.x_out[i * n + rid[r]] = y[r][i];
+                a.k_out[i * n + rid[r]] = y[r][RG_DIM + i];
+            }
+            if (a.t_out) a.t_out[rid[r]] = t[r];
+            if (a.status_out) a.status_out[rid[r]] = st[r];
+            if (a.steps_out) a.steps_out[rid[r]] = ns[r];
+        }
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_r1(rg_kargs a) { rg_rk4_persistent<1>(a); }
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_r2(rg_kargs a) { rg_rk4_persistent<2>(a); }
+
+// ------------------------------------------------------------ plain RK4 --
+// One step per launch: load state, one step, store state (the paper's
+// setter-map loop).  State lives in x_out/k_out/s_t/s_st/s_acc.
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_plain_init(rg_kargs a) {
+    if (a.traj_D) rg_stage_tables(a);  // uniform condition: every thread reaches the barrier
+    const long long n = a.n;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run) return;
+    double y[RG_NY];
+    for (int i = 0; i < RG_DIM; i++) {
+        y[i] = a.x0[i * n + r];
+        y[RG_DIM + i] = a.k0[i * n + r];
+        a.x_out[i * n + r] = y[i];
+        a.k_out[i * n + r] = y[RG_DIM + i];
+    }
+    const double t = a.t0 ? a.t0[r] : 0.0;
+    a.s_t[r] = t;
+    a.s_st[r] = RG_RAY_OK;
+    a.s_acc[r] = 0;
+    if (a.store_every > 0) {
+        for (int c = 0; c < RG_NY; c++) a.traj[(long long)c * n + r] = y[c];
+        if (a.traj_D) a.traj_D[r] = rg_D(y, a.omega[r], t, rg_params(a));
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_plain_step(rg_kargs a) {
+    rg_stage_tables(a);
+    const long long n = a.n;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run) return;
+    const rg_P P = rg_params(a);
+    double y[RG_NY], yn[RG_NY];
+    for (int i = 0; i < RG_DIM; i++) {
+        y[i] = a.x_out[i * n + r];
+        y[RG_DIM + i] = a.k_out[i * n + r];
+    }
+    double t = a.s_t[r];
+    int st = a.s_st[r];
+    const double om = a.omega[r];
+    if (a.ckpt_idx >= 0) {
+        double *cp = a.ckpt + (long long)a.ckpt_idx * (RG_NY + 1) * n + r;
+        for (int c = 0; c < RG_NY; c++) cp[(long long)c * n] = y[c];
+        cp[(long long)RG_NY * n] = t;
+    }
+    if (st == RG_RAY_OK) {
+        rg_rk4_step(y, om, t, a.dt, P, yn);
+        if (rg_finite(yn)) {
+            for (int c = 0; c < RG_NY; c++) y[c] = yn[c];
+            t = t + a.dt;
+            a.s_acc[r] += 1;
+            if (a.has_box && rg_outside(a, y)) st = RG_RAY_EXITED_BOX;
+            for (int i = 0; i < RG_DIM; i++) {
+                a.x_out[i * n + r] = y[i];
+                a.k_out[i * n + r] = y[RG_DIM + i];
+            }
+            a.s_t[r] = t;
+        } else {
+            st = RG_RAY_NONFINITE;
+        }
+        a.s_st[r] = st;
+    }
+    if (a.snap >= 0) {
+        double *tp = a.traj + (long long)a.snap * RG_NY * n + r;
+        for (int c = 0; c < RG_NY; c++) tp[(long long)c * n] = y[c];
+        if (a.traj_D) a.traj_D[(long long)a.snap * n + r] = rg_D(y, om, t, P);
+    }
+}
+
+// Copy the plain-mode state to the optional outputs.
+extern "C" __global__ void __launch_bounds__(512) rg_plain_finish(rg_kargs a) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run) return;
+    if (a.t_out) a.t_out[r] = a.s_t[r];
+    if (a.status_out) a.status_out[r] = a.s_st[r];
+    if (a.steps_out) a.steps_out[r] = a.s_acc[r];
+}
+
+// ----------------------------------------------------- Dormand-Prince 5(4) --
+// Published tableau (Dormand & Prince 1980).
+#define DPA21 (1.0 / 5.0)
+#define DPA31 (3.0 / 40.0)
+#define DPA32 (9.0 / 40.0)
+#define DPA41 (44.0 / 45.0)
+#define DPA42 (-56.0 / 15.0)
+#define DPA43 (32.0 / 9.0)
+#define DPA51 (19372.0 / 6561.0)
+#define DPA52 (-25360.0 / 2187.0)
+#define DPA53 (64448.0 / 6561.0)
+#define DPA54 (-212.0 / 729.0)
+#define DPA61 (9017.0 / 3168.0)
+#define DPA62 (-355.0 / 33.0)
+#define DPA63 (46732.0 / 5247.0)
+#define DPA64 (49.0 / 176.0)
+#define DPA65 (-5103.0 / 18656.0)
+#define DPB1 (35.0 / 384.0)
+#define DPB3 (500.0 / 1113.0)
+#define DPB4 (125.0 / 192.0)
+#define DPB5 (-2187.0 / 6784.0)
+#define DPB6 (11.0 / 84.0)
+// error weights b5 - b4
+#define DPE1 (35.0 / 384.0 - 5179.0 / 57600.0)
+#define DPE3 (500.0 / 1113.0 - 7571.0 / 16695.0)
+#define DPE4 (125.0 / 192.0 - 393.0 / 640.0)
+#define DPE5 (-2187.0 / 6784.0 - -92097.0 / 339200.0)
+#define DPE6 (11.0 / 84.0 - 187.0 / 2100.0)
+#define DPE7 (0.0 - 1.0 / 40.0)
+
+// Step factor 0.9 err^(-1/5) rounded down to a multiple of 1/32 and clipped
+// to [0.2, facmax]; the rounding makes the next step an exactly
+// reproducible function of err except at the rounding points.
+__device__ __forceinline__ double rg_dp_factor(double err, double facmax) {
+    double fac = 0.9 * pow(err, -0.2);
+    fac = floor(32.0 * fac) / 32.0;
+    if (!(fac >= 0.2)) fac = 0.2;
+    if (fac > facmax) fac = facmax;
+    return fac;
+}
+
+struct rg_dp_ray {
+    double y[RG_NY], k1[RG_NY];
+    double t, h, fm, om;
+    int acc, att, budget, st;  // st < 0: still running
+};
+
+// One Dormand-Prince attempt with the termination tests that precede and
+// follow it.  Sets r.st >= 0 when the ray is finished.
+__device__ __forceinline__ void rg_dp_attempt(const rg_kargs &a, const rg_P &P, rg_dp_ray &r) {
+    if (r.acc >= r.budget || r.att >= 4 * r.budget) { r.st = RG_RAY_BUDGET; return; }
+    if (a.t_end > 0.0 && r.t >= a.t_end) { r.st = RG_RAY_OK; return; }
+    double hs = r.h;
+    if (a.t_end > 0.0 && r.t + hs > a.t_end) hs = a.t_end - r.t;
+    double k2[RG_NY], k3[RG_NY], k4[RG_NY], k5[RG_NY], k6[RG_NY], k7[RG_NY], Y[RG_NY];
+    const double *y = r.y, *k1 = r.k1;
+    for (int i = 0; i < RG_NY; i++) Y[i] = fma(hs, DPA21 * k1[i], y[i]);
+    rg_rhs(Y, r.om, r.t + hs * (1.0 / 5.0), P, k2);
+    for (int i = 0; i < RG_NY; i++) Y[i] = fma(hs, fma(DPA32, k2[i], DPA31 * k1[i]), y[i]);
+    rg_rhs(Y, r.om, r.t + hs * (3.0 / 10.0), P, k3);
+    for (int i = 0; i < RG_NY; i++)
+        Y[i] = fma(hs, fma(DPA43, k3[i], fma(DPA42, k2[i], DPA41 * k1[i])), y[i]);
+    rg_rhs(Y, r.om, r.t + hs * (4.0 / 5.0), P, k4);
+    for (int i = 0; i < RG_NY; i++)
+        Y[i] = fma(hs, fma(DPA54, k4[i], fma(DPA53, k3[i], fma(DPA52, k2[i], DPA51 * k1[i]))), y[i]);
+    rg_rhs(Y, r.om, r.t + hs * (8.0 / 9.0), P, k5);
+    for (int i = 0; i < RG_NY; i++)
+        Y[i] = fma(hs, fma(DPA65, k5[i], fma(DPA64, k4[i], fma(DPA63, k3[i], fma(DPA62, k2[i], DPA61 * k1[i])))), y[i]);
+    rg_rhs(Y, r.om, r.t + hs, P, k6);
+    // 5th-order solution (also the 7th stage point, FSAL)
+    double y5[RG_NY];
+    for (int i = 0; i < RG_NY; i++)
+        y5[i] = fma(hs, fma(DPB6, k6[i], fma(DPB5, k5[i], fma(DPB4, k4[i], fma(DPB3, k3[i], DPB1 * k1[i])))), y[i]);
+    rg_rhs(y5, r.om, r.t + hs, P, k7);
+    double sum = 0.0;
+    for (int i = 0; i < RG_NY; i++) {
+        double e = fma(DPE7, k7[i], fma(DPE6, k6[i], fma(DPE5, k5[i], fma(DPE4, k4[i], fma(DPE3, k3[i], DPE1 * k1[i])))));
+        e = hs * e;
+        const double ay = fabs(y[i]), ay5 = fabs(y5[i]);
+        const double sc = fma(a.rtol, ay > ay5 ? ay : ay5, a.atol);
+        const double q = e / sc;
+        sum = fma(q, q, sum);
+    }
+    const double err = sqrt(sum / (double)RG_NY);
+    r.att++;
+    if (err <= 1.0 && rg_finite(y5) && rg_finite(k7)) {
+        for (int i = 0; i < RG_NY; i++) { r.y[i] = y5[i]; r.k1[i] = k7[i]; }
+        r.t = r.t + hs;
+        r.acc++;
+        r.h = hs * rg_dp_factor(err, r.fm);
+        r.fm = 5.0;
+        if (a.has_box && rg_outside(a, r.y)) { r.st = RG_RAY_EXITED_BOX; return; }
+    } else {
+        r.h = hs * rg_dp_factor(err > 1.0 ? err : __builtin_inf(), 1.0);
+        r.fm = 1.0;
+    }
+    if (r.h < a.hmin) r.st = RG_RAY_STEP_UNDERFLOW;
+}
+
+__device__ __forceinline__ void rg_dp_load(const rg_kargs &a, const rg_P &P, long long id, rg_dp_ray &r) {
+    const long long n = a.n;
+    for (int i = 0; i < RG_DIM; i++) {
+        r.y[i] = a.x0[i * n + id];
+        r.y[RG_DIM + i] = a.k0[i * n + id];
+    }
+    r.t = a.t0 ? a.t0[id] : 0.0;
+    r.om = a.omega[id];
+    r.h = a.h0;
+    r.fm = 5.0;
+    r.acc = 0;
+    r.att = 0;
+    r.budget = a.budget ? a.budget[id] : a.max_steps;
+    if (a.budget_cap > 0 && r.budget > a.budget_cap) r.budget = a.budget_cap;
+    r.st = -1;
+}
+
+__device__ __forceinline__ void rg_dp_store(const rg_kargs &a, long long id, rg_dp_ray &r) {
+    const long long n = a.n;
+    if (!rg_finite(r.y)) r.st = RG_RAY_NONFINITE;
+    for (int i = 0; i < RG_DIM; i++) {
+        a.x_out[i * n + id] = r.y[i];
+        a.k_out[i * n + id] = r.y[RG_DIM + i];
+    }
+    if (a.t_out) a.t_out[id] = r.t;
+    if (a.status_out) a.status_out[id] = r.st;
+    if (a.steps_out) a.steps_out[id] = r.acc;
+}
+
+// Persistent adaptive kernel with wave-level compaction: every `compact`
+// attempts (and whenever the whole wave is idle) the finished lanes of a
+// wave are refilled with new rays from a global queue.  One atomic per wave
+// reserves as many rays as the wave has free lanes; ballot + popcount give
+// each free lane its rank, so the new rays land in the free lanes in order.
+extern "C" __global__ void __launch_bounds__(512) rg_dopri_persistent(rg_kargs a) {
+    rg_stage_tables(a);
+    const rg_P P = rg_params(a);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    rg_dp_ray r;
+    r.st = 0;
+    long long id = -1;
+    bool alive = false, need_k1 = false, exhausted = false;
+    int iter = 0;
+    const int C = a.compact;
+    for (;;) {
+        const unsigned long long live = __ballot(alive);
+        const bool due = (live == 0ull) || (C > 0 && iter % C == 0);
+        if (!exhausted && due && live != ~0ull) {
+            const unsigned long long freem = ~live;
+            const int nfree = __popcll(freem);
+            const int leader = __ffsll((long long)freem) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)nfree);
+            base = __shfl(base, leader);
+            if (!alive) {
+                const long long cand = (long long)base + __popcll(freem & below);
+                if (cand < a.n_run) {
+                    id = cand;
+                    rg_dp_load(a, P, id, r);
+                    alive = true;
+                    need_k1 = true;
+                }
+            }
+            if ((long long)base + nfree >= a.n_run) exhausted = true;
+        }
+        if (__ballot(alive) == 0ull) break;
+        iter++;
+        if (alive) {
+            if (need_k1) {
+                rg_rhs(r.y, r.om, r.t, P, r.k1);
+                need_k1 = false;
+            }
+            rg_dp_attempt(a, P, r);
+            if (r.st >= 0) {
+                rg_dp_store(a, id, r);
+                alive = false;
+            }
+        }
+    }
+}
+
+// Plain adaptive form: one attempt per launch for every ray, state in HBM.
+extern "C" __global__ void __launch_bounds__(512) rg_dopri_plain_init(rg_kargs a) {
+    rg_stage_tables(a);
+    const long long n = a.n;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= a.n_run) return;
+    const rg_P P = rg_params(a);
+    rg_dp_ray r;
+    rg_dp_load(a, P, id, r);
+    rg_rhs(r.y, r.om, r.t, P, r.k1);
+    for (int c = 0; c < RG_NY; c++) {
+        a.s_y[(long long)c * n + id] = r.y[c];
+        a.s_k1[(long long)c * n + id] = r.k1[c];
+    }
+    a.s_t[id] = r.t;
+    a.s_h[id] = r.h;
+    a.s_fm[id] = r.fm;
+    a.s_acc[id] = 0;
+    a.s_att[id] = 0;
+    a.s_st[id] = -1;
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_dopri_plain_step(rg_kargs a) {
+    rg_stage_tables(a);
+    const long long n = a.n;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= a.n_run) return;
+    int st = a.s_st[id];
+    if (st >= 0) return;
+    const rg_P P = rg_params(a);
+    rg_dp_ray r;
+    for (int c = 0; c < RG_NY; c++) {
+        r.y[c] = a.s_y[(long long)c * n + id];
+        r.k1[c] = a.s_k1[(long long)c * n + id];
+    }
+    r.t = a.s_t[id];
+    r.h = a.s_h[id];
+    r.fm = a.s_fm[id];
+    r.om = a.omega[id];
+    r.acc = a.s_acc[id];
+    r.att = a.s_att[id];
+    r.budget = a.budget ? a.budget[id] : a.max_steps;
+    if (a.budget_cap > 0 && r.budget > a.budget_cap) r.budget = a.budget_cap;
+    r.st = -1;
+    rg_dp_attempt(a, P, r);
+    for (int c = 0; c < RG_NY; c++) {
+        a.s_y[(long long)c * n + id] = r.y[c];
+        a.s_k1[(long long)c * n + id] = r.k1[c];
+    }
+    a.s_t[id] = r.t;
+    a.s_h[id] = r.h;
+    a.s_fm[id] = r.fm;
+    a.s_acc[id] = r.acc;
+    a.s_att[id] = r.att;
+    a.s_st[id] = r.st;
+    if (r.st >= 0) rg_dp_store(a, id, r);
+    else if (a.count_alive) atomicAdd(a.counter, 1);
+}
+
+// ----------------------------------------------------------------- utils --
+extern "C" __global__ void __launch_bounds__(512) rg_fill_f64(rg_kargs a) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.fill_n) a.fill_p[i] = a.fill_v;
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_eval_points(rg_kargs a) {
+    rg_stage_tables(a);
+    const long long n = a.n;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run) return;
+    const rg_P P = rg_params(a);
+    double y[RG_NY], f[RG_NY];
+    for (int c = 0; c < RG_NY; c++) y[c] = a.x0[(long long)c * n + r];
+    const double om = a.omega[r], t = a.t0 ? a.t0[r] : 0.0;
+    if (a.x_out) {
+        rg_rhs(y, om, t, P, f);
+        for (int c = 0; c < RG_NY; c++) a.x_out[(long long)c * n + r] = f[c];
+    }
+    if (a.t_out) a.t_out[r] = rg_D(y, om, t, P);
+}
+
+// --------------------------------------------------------------- adjoint --
+#if RG_HAS_VJP
+#define RG_NGRAD1 (RG_NGRAD > 0 ? RG_NGRAD : 1)
+__shared__ double rg_red_lds[8 * RG_NGRAD1];
+
+// Discrete adjoint of the RK4 map (exact transpose of one step):
+//   Kb4 = dt/6 lam,            Yb4 = J(Y4)^T Kb4
+//   Kb3 = dt/3 lam + dt Yb4,   Yb3 = J(Y3)^T Kb3
+//   Kb2 = dt/3 lam + dt/2 Yb3, Yb2 = J(Y2)^T Kb2
+//   Kb1 = dt/6 lam + dt/2 Yb2, Yb1 = J(Y1)^T Kb1
+//   lam <- lam + Yb1 + Yb2 + Yb3 + Yb4,  dL/dtheta += sum_i (df/dtheta(Y_i))^T Kb_i
+// Segments between forward checkpoints are walked last to first; the states
+// of a segment are recomputed from its checkpoint into per-lane scratch
+// (coalesced [j][c][lane]) and read back in reverse.
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_adjoint(rg_kargs a) {
+    rg_stage_tables(a);
+#if RG_NSPLTAB > 0
+    for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) rg_spl_grad_lds[i] = 0.0;
+    __syncthreads();
+#endif
+    const rg_P P = rg_params(a);
+    rg_GA G;
+    G.init();
+    double gp[RG_NGRAD1];
+    for (int i = 0; i < RG_NGRAD1; i++) gp[i] = 0.0;
+    const long long n = a.n;
+    const long long GL = (long long)gridDim.x * blockDim.x;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double dt = a.dt, h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
+    const int ce = a.ckpt_every;
+    const long long SL = a.scratch_lanes;
+    for (long long rid = gid; rid < a.n_run; rid += GL) {
+        double lam[RG_NY];
+        for (int i = 0; i < RG_DIM; i++) {
+            lam[i] = a.lam_x[i * n + rid];
+            lam[RG_DIM + i] = a.lam_k ? a.lam_k[i * n + rid] : 0.0;
+        }
+        const int ns = a.steps_out[rid];
+        const double om = a.omega[rid];
+        const int nseg = (a.n_steps + ce - 1) / ce;
+        for (int seg = nseg - 1; seg >= 0; seg--) {
+            const int s0 = seg * ce;
+            if (s0 >= ns) continue;
+            const int s1 = s0 + ce < ns ? s0 + ce : ns;
+            double y[RG_NY], t;
+            const double *cp = a.ckpt + (long long)seg * (RG_NY + 1) * n + rid;
+            for (int c = 0; c < RG_NY; c++) y[c] = cp[(long long)c * n];
+            t = cp[(long long)RG_NY * n];
+            for (int j = s0; j < s1; j++) {
+                double *sp = a.scratch + (long long)(j - s0) * (RG_NY + 1) * SL + gid;
+                for (int c = 0; c < RG_NY; c++) sp[(long long)c * SL] = y[c];
+                sp[(long long)RG_NY * SL] = t;
+                double yn[RG_NY];
+                rg_rk4_step(y, om, t, dt, P, yn);
+                for (int c = 0; c < RG_NY; c++) y[c] = yn[c];
+                t = t + dt;
+            }
+            for (int j = s1 - 1; j >= s0; j--) {
+                const double *sp = a.scratch + (long long)(j - s0) * (RG_NY + 1) * SL + gid;
+                double Y1[RG_NY], Y2[RG_NY], Y3[RG_NY], Y4[RG_NY], K[RG_NY];
+                for (int c = 0; c < RG_NY; c++) Y1[c] = sp[(long long)c * SL];
+                const double tj = sp[(long long)RG_NY * SL];
+                rg_rhs(Y1, om, tj, P, K);
+                for (int c = 0; c < RG_NY; c++) Y2[c] = fma(h2, K[c], Y1[c]);
+                rg_rhs(Y2, om, tj + h2, P, K);
+                for (int c = 0; c < RG_NY; c++) Y3[c] = fma(h2, K[c], Y1[c]);
+                rg_rhs(Y3, om, tj + h2, P, K);
+                for (int c = 0; c < RG_NY; c++) Y4[c] = fma(dt, K[c], Y1[c]);
+                double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY];
+                for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
+                rg_vjp(Y4, om, tj + dt, P, Kb, Yb, gp, G);
+                for (int c = 0; c < RG_NY; c++) { lsum[c] = Yb[c]; Kb[c] = fma(dt, Yb[c], dt3 * lam[c]); }
+                rg_vjp(Y3, om, tj + h2, P, Kb, Yb, gp, G);
+                for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt3 * lam[c]); }
+                rg_vjp(Y2, om, tj + h2, P, Kb, Yb, gp, G);
+                for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt6 * lam[c]); }
+                rg_vjp(Y1, om, tj, P, Kb, Yb, gp, G);
+                for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + (lsum[c] + Yb[c]);
+            }
+        }
+        for (int i = 0; i < RG_DIM; i++) {
+            if (a.gx0) a.gx0[i * n + rid] = lam[i];
+            if (a.gk0) a.gk0[i * n + rid] = lam[RG_DIM + i];
+        }
+    }
+    // parameter-gradient partials of this workgroup (fixed-order for scalars)
+#if RG_NSPLTAB > 0
+    for (int k = 0; k < RG_NSPLTAB; k++) G.flush(k);
+#endif
+    if (a.gpart) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        for (int s = 0; s < RG_NGRAD; s++) {
+            double v = gp[s];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) rg_red_lds[wave * RG_NGRAD1 + s] = v;
+        }
+        __syncthreads();
+        double *out = a.gpart + (long long)blockIdx.x * a.part_stride;
+        for (int s = threadIdx.x; s < RG_NGRAD; s += blockDim.x) {
+            double v = 0.0;
+            for (int w = 0; w < nw; w++) v += rg_red_lds[w * RG_NGRAD1 + s];
+            out[s] = v;
+        }
+#if RG_NSPLTAB > 0
+        for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) out[RG_NGRAD + i] = rg_spl_grad_lds[i];
+#endif
+    }
+}
+
+// Sum the per-workgroup partials in workgroup order and scatter them to the
+// parameter gradient arrays (already zeroed).
+extern "C" __global__ void __launch_bounds__(512) rg_grad_finalize(rg_kargs a) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.part_stride) return;
+    double v = 0.0;
+    for (int p = 0; p < a.n_part; p++) v += a.gpart[(long long)p * a.part_stride + e];
+    if (e < RG_NGRAD) {
+#if RG_NGRAD > 0
+        double *dst = a.dparams[rg_grad_param[e]];
+        if (dst) dst[rg_grad_elem[e]] = v;
+#endif
+    } else {
+#if RG_NSPLTAB > 0
+        const long long i = e - RG_NGRAD;
+        for (int k = 0; k < RG_NSPLTAB; k++)
+            if (i >= rg_spl_off[k] && i < rg_spl_off[k] + rg_spl_len[k]) {
+                double *dst = a.dparams[rg_spl_param[k]];
+                if (dst) dst[i - rg_spl_off[k]] = v;
+            }
+#endif
+    }
+}
+#endif

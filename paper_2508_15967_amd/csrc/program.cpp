@@ -1,0 +1,221 @@
+// From a dispersion relation D to a gfx950 code object.
+//
+// Ray equations by implicit differentiation (paper, eqs. 2-3):
+//   dx/dt = -(dD/dk) / (dD/domega),   dk/dt = (dD/dx) / (dD/domega)
+// built with the graph's df, so reduction and hash-consing apply to the
+// derivatives as they are built.  One reciprocal of dD/domega is shared by
+// all 2*dim components.  For the adjoint the scalar s = sum_j v_j f_j(y) is
+// built with seed variables v_j; df of s with respect to each state
+// component, each parameter element and each spline node gives the
+// vector-Jacobian products J^T v and (df/dtheta)^T v.
+#include <hip/hiprtc.h>
+
+#include <chrono>
+#include <cstring>
+#include <sstream>
+
+#include "emit.hpp"
+#include "program.hpp"
+
+#include "_embedded_kernels.inc"
+
+namespace rg {
+
+uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
+    const unsigned char *p = (const unsigned char *)data;
+    for (size_t i = 0; i < n; i++) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static std::string int_array(const char *name, const std::vector<int> &v) {
+    std::ostringstream os;
+    os << "__constant__ int " << name << "[" << (v.empty() ? 1 : v.size()) << "] = {";
+    if (v.empty()) os << "0";
+    for (size_t i = 0; i < v.size(); i++) os << (i ? ", " : "") << v[i];
+    os << "};\n";
+    return os.str();
+}
+
+rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_program *p) {
+    auto t0 = std::chrono::steady_clock::now();
+    const uint32_t d = g.dim(), ny = 2 * d;
+    p->dim = d;
+    p->n_params = (uint32_t)g.params().size();
+    if (p->n_params > RG_KMAX_PARAMS) return fail(RG_EUNSUPPORTED, "at most 8 parameter arrays");
+    for (const ParamDef &pd : g.params()) p->param_len.push_back(pd.len);
+    p->has_vjp = opts.want_adjoint != 0;
+    p->compile_only = opts.compile_only != 0;
+
+    // ---- ray equations
+    std::vector<uint32_t> yv(ny);
+    for (uint32_t i = 0; i < d; i++) {
+        yv[i] = g.var(VK_X, i);
+        yv[d + i] = g.var(VK_K, i);
+    }
+    const uint32_t om = g.var(VK_OMEGA, 0);
+    const uint32_t Dw = g.df(D, om);
+    if (g.is_const(Dw, 0.0)) return fail(RG_EINVAL, "dD/domega is identically zero");
+    const uint32_t inv = g.div(g.constant(1.0), Dw);
+    std::vector<uint32_t> f(ny);
+    for (uint32_t i = 0; i < d; i++) {
+        f[i] = g.neg(g.mul(g.df(D, yv[d + i]), inv));
+        f[d + i] = g.mul(g.df(D, yv[i]), inv);
+    }
+
+    // ---- spline tables used by the program
+    std::vector<uint32_t> roots(f.begin(), f.end());
+    roots.push_back(D);
+    std::vector<int> table_slot(p->n_params, -1);
+    for (uint32_t n : g.reachable(roots)) {
+        const Node &nd = g.node(n);
+        if (nd.op != SPLINE) continue;
+        const SplineDef &s = g.splines()[(size_t)nd.val];
+        if (table_slot[s.param] >= 0) continue;
+        if (g.params()[s.param].len < s.nx * s.ny)
+            return fail(RG_EINVAL, "spline parameter shorter than nx*ny");
+        table_slot[s.param] = (int)p->spl_param.size();
+        p->spl_param.push_back((int)s.param);
+        p->spl_off.push_back(p->spl_total);
+        p->spl_len.push_back((int)(s.nx * s.ny));
+        p->spl_ny.push_back((int)s.ny);
+        p->spl_total += (int)(s.nx * s.ny);
+    }
+    if (p->spl_total > 8192)
+        return fail(RG_EUNSUPPORTED, "spline tables larger than 8192 coefficients (LDS staging)");
+
+    // ---- emit rhs and D
+    std::ostringstream fs;
+    Flops fl_rhs, fl_D, fl_vjp;
+    {
+        FunctionSpec spec;
+        spec.signature =
+            "RG_FN void rg_rhs(const double *__restrict__ y, const double om, const double t, "
+            "const rg_P &P, double *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
+        for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
+        fs << emit_function(g, spec, table_slot, &fl_rhs);
+    }
+    {
+        FunctionSpec spec;
+        spec.signature =
+            "RG_FN double rg_D(const double *__restrict__ y, const double om, const double t, "
+            "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
+        spec.outputs.push_back({D, "", false});
+        spec.returns_value = true;
+        fs << emit_function(g, spec, table_slot, &fl_D);
+    }
+    p->info.n_nodes_rhs = fl_rhs.ops;
+
+    // ---- emit the VJP
+    if (p->has_vjp) {
+        uint32_t s = g.constant(0.0);
+        for (uint32_t j = 0; j < ny; j++) s = g.add(s, g.mul(g.var(VK_SEED, j), f[j]));
+        FunctionSpec spec;
+        spec.signature =
+            "RG_FN void rg_vjp(const double *__restrict__ y, const double om, const double t, "
+            "const rg_P &P, const double *__restrict__ av, double *__restrict__ jv, "
+            "double *__restrict__ gp, rg_GA &G) {\n  (void)om; (void)t; (void)P; (void)gp; (void)G;";
+        for (uint32_t j = 0; j < ny; j++) spec.outputs.push_back({g.df(s, yv[j]), "jv[" + std::to_string(j) + "]", false});
+        std::vector<uint32_t> freach = g.reachable(f);
+        for (uint32_t n : freach) {
+            const Node &nd = g.node(n);
+            if (nd.op == PARAM) {
+                int slot = (int)p->grad_param.size();
+                p->grad_param.push_back(nd.aux);
+                p->grad_elem.push_back((int)nd.val);
+                spec.outputs.push_back({g.df(s, n), "gp[" + std::to_string(slot) + "]", true});
+            }
+        }
+        for (uint32_t n : freach) {
+            const Node &nd = g.node(n);
+            if (nd.op == SPLINE) spec.spline_seeds.push_back({n, g.df(s, n)});
+        }
+        fs << emit_function(g, spec, table_slot, &fl_vjp);
+        p->info.n_nodes_vjp = fl_vjp.ops;
+    }
+    p->functions_src = fs.str();
+
+    // ---- configuration header
+    std::ostringstream cs;
+    cs << "#pragma once\n#define RG_DIM " << d << "\n#define RG_NY " << ny << "\n#define RG_NPARAM "
+       << p->n_params << "\n#define RG_NGRAD " << p->grad_param.size() << "\n#define RG_NSPLTAB "
+       << p->spl_param.size() << "\n#define RG_SPL_TOTAL " << (p->spl_total ? p->spl_total : 1)
+       << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n";
+    cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)
+       << int_array("rg_spl_len", p->spl_len) << int_array("rg_spl_ny", p->spl_ny)
+       << int_array("rg_grad_param", p->grad_param) << int_array("rg_grad_elem", p->grad_elem);
+    p->config_src = cs.str();
+
+    // ---- flop accounting
+    rg_program_info &I = p->info;
+    I.struct_size = sizeof(rg_program_info);
+    I.dim = d;
+    I.n_params = p->n_params;
+    I.n_grad_slots = (uint32_t)p->grad_param.size();
+    I.rhs_flops_alg = fl_rhs.alg;
+    I.rhs_flops_issued = fl_rhs.issued;
+    // RK4 update: per component 3 stage fma + fma, fma, add + final fma = 13
+    // flops, plus t += dt and the two step constants.
+    const double upd = 13.0 * ny + 1.0;
+    I.rk4_step_flops_alg = 4 * fl_rhs.alg + upd;
+    I.rk4_step_flops_issued = 4 * fl_rhs.issued + upd;
+    // DOPRI attempt: 6 new right-hand sides; stage sums 2s+1 flops per
+    // component for s = 1..6 (48), error estimate 11 + scale 2 + div 1 +
+    // square-accumulate 2 (16), plus sqrt, mean and the step factor.
+    const double dp = 64.0 * ny + 8.0;
+    const IssuedWeights &w = issued_weights();
+    I.dopri_attempt_flops_alg = 6 * fl_rhs.alg + dp;
+    I.dopri_attempt_flops_issued = 6 * fl_rhs.issued + dp - 4.0 + w.sqrt + 2 * w.div + w.exp + w.log;
+    if (p->has_vjp) {
+        I.vjp_flops_alg = fl_vjp.alg;
+        I.vjp_flops_issued = fl_vjp.issued;
+        // reverse of one step: recompute (one RK4 step) + 3 stage RHS + 4 VJP
+        // + stage states (3 fma) + recurrence (per component: 3 fma, 3 add,
+        // 1 mul, 1 add = 12 flops)
+        const double rec = (3 * 2 + 12) * ny;
+        I.adj_step_flops_alg = I.rk4_step_flops_alg + 3 * fl_rhs.alg + 4 * fl_vjp.alg + rec;
+        I.adj_step_flops_issued = I.rk4_step_flops_issued + 3 * fl_rhs.issued + 4 * fl_vjp.issued + rec;
+    }
+
+    // ---- full source and hipRTC compile
+    p->full_src = std::string("// generated by raygraph\n") + RG_SRC_KERNELS;
+    p->hash = fnv1a(p->config_src.data(), p->config_src.size());
+    p->hash = fnv1a(p->functions_src.data(), p->functions_src.size(), p->hash);
+    p->hash = fnv1a(p->full_src.data(), p->full_src.size(), p->hash);
+    I.source_hash = p->hash;
+
+    const char *arch = opts.arch ? opts.arch : "gfx950";
+    std::string arch_opt = std::string("--offload-arch=") + arch;
+    int olvl = opts.opt_level > 0 ? opts.opt_level : 3;
+    std::string o_opt = "-O" + std::to_string(olvl);
+    const char *hnames[] = {"rg_kargs.h", "rg_config.h", "rg_prelude.h", "rg_functions.h"};
+    std::string fsrc = p->functions_src;
+    const char *hsrcs[] = {RG_SRC_KARGS, p->config_src.c_str(), RG_SRC_PRELUDE, fsrc.c_str()};
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, p->full_src.c_str(), "raygraph_kernels.hip", 4, hsrcs, hnames) !=
+        HIPRTC_SUCCESS)
+        return fail(RG_ECOMPILE, "hiprtcCreateProgram failed");
+    // no FP contraction beyond the fma written in the source; no packed FP32
+    const char *copts[] = {arch_opt.c_str(), o_opt.c_str(), "-ffp-contract=off", "-std=c++17",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    hiprtcResult rc = hiprtcCompileProgram(prog, 8, copts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(RG_ECOMPILE, std::string("hipRTC: ") + hiprtcGetErrorString(rc) + "\n" + log);
+    }
+    size_t cs_ = 0;
+    hiprtcGetCodeSize(prog, &cs_);
+    p->code.resize(cs_);
+    hiprtcGetCode(prog, p->code.data());
+    hiprtcDestroyProgram(&prog);
+    I.compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return RG_OK;
+}
+
+}  // namespace rg

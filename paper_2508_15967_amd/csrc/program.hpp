@@ -1,0 +1,69 @@
+// Compiled program: generated source, gfx950 code object, kernel handles,
+// workspace, autotuning results and captured hipGraphs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/raygraph.h"
+#include "graph.hpp"
+#include "kernels/rg_kargs.h"
+
+struct TuneEntry {
+    int block = 256, rpl = 1, compact = 64;
+};
+
+struct GraphEntry {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct rg_program {
+    uint32_t dim = 0;
+    uint32_t n_params = 0;
+    std::vector<uint32_t> param_len;
+    bool has_vjp = false;
+    bool compile_only = false;
+    // gradient layout
+    std::vector<int> grad_param, grad_elem;       // scalar slots
+    std::vector<int> spl_param, spl_off, spl_len, spl_ny;
+    int spl_total = 0;
+    // sources and code
+    std::string config_src, functions_src, full_src;
+    std::vector<char> code;
+    uint64_t hash = 0;
+    rg_program_info info{};
+    // runtime
+    int device = -1;
+    int n_cu = 0;
+    hipModule_t module = nullptr;
+    std::map<std::string, hipFunction_t> kernels;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::map<std::string, TuneEntry> tune;
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+    rg_launch_info last{};
+
+    ~rg_program();
+};
+
+namespace rg {
+// Thread-local error message handling (capi.cpp).
+rg_status fail(rg_status code, const std::string &msg);
+// Build sources and compile (program.cpp).
+rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_program *p);
+// Runtime (runtime.cpp).
+rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s);
+rg_status adjoint(rg_program *p, const rg_adjoint_desc &d, hipStream_t s);
+rg_status eval_points(rg_program *p, uint32_t n, const double *y, const double *omega,
+                      const double *t, const double *const *params, double *f, double *D,
+                      hipStream_t s);
+uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull);
+}  // namespace rg

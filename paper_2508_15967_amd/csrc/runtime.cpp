@@ -1,0 +1,620 @@
+// Runtime: module loading, workspace, argument validation, launch
+// sequences (persistent or one-launch-per-step), hipGraph capture and
+// replay, autotuning, and the adjoint pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "program.hpp"
+
+namespace rg {
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(RG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+#define RGCHK(expr)                  \
+    do {                             \
+        rg_status s_ = (expr);       \
+        if (s_ != RG_OK) return s_;  \
+    } while (0)
+
+static const char *const KERNELS[] = {
+    "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
+    "rg_dopri_persistent", "rg_dopri_plain_init", "rg_dopri_plain_step", "rg_fill_f64",
+    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize"};
+
+static void drop_graphs(rg_program *p) {
+    for (GraphEntry &ge : p->graphs) {
+        if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+        if (ge.graph) (void)hipGraphDestroy(ge.graph);
+    }
+    p->graphs.clear();
+}
+
+}  // namespace rg
+
+rg_program::~rg_program() {
+    rg::drop_graphs(this);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ws) (void)hipFree(ws);
+    if (module) (void)hipModuleUnload(module);
+}
+
+namespace rg {
+
+static rg_status ensure_module(rg_program *p) {
+    if (p->compile_only) return fail(RG_ESTATE, "program was compiled with compile_only=1");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (p->module && p->device == dev) return RG_OK;
+    if (p->module) {
+        drop_graphs(p);
+        if (p->ws) (void)hipFree(p->ws);
+        p->ws = nullptr;
+        p->ws_bytes = 0;
+        (void)hipModuleUnload(p->module);
+        p->module = nullptr;
+        p->kernels.clear();
+    }
+    HIPCHK(hipModuleLoadData(&p->module, p->code.data()));
+    for (const char *k : KERNELS) {
+        hipFunction_t f = nullptr;
+        if (hipModuleGetFunction(&f, p->module, k) == hipSuccess) p->kernels[k] = f;
+    }
+    (void)hipGetLastError();
+    HIPCHK(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    p->device = dev;
+    return RG_OK;
+}
+
+static rg_status kernel(rg_program *p, const char *name, hipFunction_t *f) {
+    auto it = p->kernels.find(name);
+    if (it == p->kernels.end()) return fail(RG_EUNSUPPORTED, std::string("kernel not in module: ") + name);
+    *f = it->second;
+    return RG_OK;
+}
+
+// A device pointer must lie inside one device allocation together with the
+// `bytes` that follow it; anything else (host memory, a stale pointer, a
+// buffer too small for the rays) is rejected before any launch.
+static rg_status check_dev(const void *ptr, size_t bytes, const char *what) {
+    if (!ptr) return fail(RG_EINVAL, std::string(what) + " is NULL");
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof at);
+    hipError_t e = hipPointerGetAttributes(&at, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RG_EINVAL, std::string(what) + " is not device memory");
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return fail(RG_EINVAL, std::string(what) + " is not device memory");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RG_EINVAL, std::string(what) + ": cannot query allocation range");
+    }
+    const char *b = (const char *)base, *q = (const char *)ptr;
+    if (q < b || (size_t)(q - b) + bytes > size)
+        return fail(RG_EINVAL, std::string(what) + " is smaller than required (" + std::to_string(bytes) + " bytes)");
+    if (((uintptr_t)ptr & 7u) != 0) return fail(RG_EINVAL, std::string(what) + " is not 8-byte aligned");
+    return RG_OK;
+}
+
+static rg_status ensure_ws(rg_program *p, size_t bytes) {
+    if (bytes <= p->ws_bytes) return RG_OK;
+    drop_graphs(p);  // captured graphs refer to the old workspace
+    if (p->ws) HIPCHK(hipFree(p->ws));
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+    size_t want = std::max<size_t>(bytes, 1 << 20);
+    if (hipMalloc(&p->ws, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RG_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    p->ws_bytes = want;
+    return RG_OK;
+}
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *r = (T *)(base + off);
+        off += count * sizeof(T);
+        return r;
+    }
+};
+
+struct Launch {
+    const char *name;
+    unsigned grid, block;
+    rg_kargs a;
+};
+
+static rg_status launch_one(rg_program *p, const Launch &L, hipStream_t s) {
+    hipFunction_t f;
+    RGCHK(kernel(p, L.name, &f));
+    if (L.grid == 0) return RG_OK;
+    void *args[] = {(void *)&L.a};
+    HIPCHK(hipModuleLaunchKernel(f, L.grid, 1, 1, L.block, 1, 1, 0, s, args, nullptr));
+    return RG_OK;
+}
+
+static std::string seq_key(const std::vector<Launch> &seq) {
+    uint64_t h = 1469598103934665603ull;
+    for (const Launch &L : seq) {
+        h = fnv1a(L.name, std::strlen(L.name), h);
+        h = fnv1a(&L.grid, sizeof L.grid, h);
+        h = fnv1a(&L.block, sizeof L.block, h);
+        h = fnv1a(&L.a, sizeof L.a, h);
+    }
+    return std::to_string(h) + ":" + std::to_string(seq.size());
+}
+
+// Run a launch sequence directly or through a cached hipGraph.
+static rg_status run_seq(rg_program *p, const std::vector<Launch> &seq, bool graph, hipStream_t s) {
+    if (!graph) {
+        for (const Launch &L : seq) RGCHK(launch_one(p, L, s));
+        return RG_OK;
+    }
+    std::string key = seq_key(seq);
+    for (GraphEntry &ge : p->graphs)
+        if (ge.key == key) {
+            HIPCHK(hipGraphLaunch(ge.exec, s));
+            return RG_OK;
+        }
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    rg_status st = RG_OK;
+    for (const Launch &L : seq) {
+        st = launch_one(p, L, p->cap_stream);
+        if (st != RG_OK) break;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != RG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(RG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(RG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (p->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        (void)hipGraphDestroy(p->graphs.front().graph);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back(GraphEntry{key, g, ex});
+    HIPCHK(hipGraphLaunch(ex, s));
+    return RG_OK;
+}
+
+static unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+static rg_status occupancy_grid(rg_program *p, const char *name, int block, long long want, unsigned *grid) {
+    hipFunction_t f;
+    RGCHK(kernel(p, name, &f));
+    int nb = 0;
+    HIPCHK(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, 0));
+    if (nb < 1) nb = 1;
+    long long cap = (long long)nb * p->n_cu;
+    *grid = (unsigned)std::max<long long>(1, std::min(cap, want));
+    return RG_OK;
+}
+
+// ------------------------------------------------------------ validation --
+
+static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
+    const uint32_t dim = p->dim, ny = 2 * dim;
+    const size_t n = d.n_rays;
+    if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
+    if (d.integrator != RG_RK4 && d.integrator != RG_DOPRI54) return fail(RG_EINVAL, "unknown integrator");
+    if (d.mode != RG_PERSISTENT && d.mode != RG_PLAIN) return fail(RG_EINVAL, "unknown mode");
+    if (d.block != 0 && d.block != 64 && d.block != 128 && d.block != 256 && d.block != 512)
+        return fail(RG_EINVAL, "block must be 0, 64, 128, 256 or 512");
+    if (d.rays_per_lane < 0 || d.rays_per_lane > 2) return fail(RG_EINVAL, "rays_per_lane must be 0, 1 or 2");
+    std::memset(&a, 0, sizeof a);
+    a.n = (long long)n;
+    a.n_run = (long long)n;
+    RGCHK(check_dev(d.x0, 8 * dim * n, "x0"));
+    RGCHK(check_dev(d.k0, 8 * dim * n, "k0"));
+    RGCHK(check_dev(d.omega, 8 * n, "omega"));
+    RGCHK(check_dev(d.x_out, 8 * dim * n, "x_out"));
+    RGCHK(check_dev(d.k_out, 8 * dim * n, "k_out"));
+    if (d.t0) RGCHK(check_dev(d.t0, 8 * n, "t0"));
+    if (d.t_out) RGCHK(check_dev(d.t_out, 8 * n, "t_out"));
+    if (d.status_out) RGCHK(check_dev(d.status_out, 4 * n, "status_out"));
+    if (d.steps_out) RGCHK(check_dev(d.steps_out, 4 * n, "steps_out"));
+    if (p->n_params > 0 && !d.params) return fail(RG_EINVAL, "params is NULL but the graph has parameters");
+    for (uint32_t i = 0; i < p->n_params; i++) {
+        RGCHK(check_dev(d.params[i], 8 * (size_t)p->param_len[i], "params[i]"));
+        a.params[i] = d.params[i];
+    }
+    a.x0 = d.x0; a.k0 = d.k0; a.t0 = d.t0; a.omega = d.omega;
+    a.x_out = d.x_out; a.k_out = d.k_out; a.t_out = d.t_out;
+    a.status_out = d.status_out; a.steps_out = d.steps_out;
+    a.has_box = d.has_box ? 1 : 0;
+    for (int i = 0; i < 3; i++) { a.box_lo[i] = d.box_lo[i]; a.box_hi[i] = d.box_hi[i]; }
+    if (d.integrator == RG_RK4) {
+        if (d.n_steps < 0) return fail(RG_EINVAL, "n_steps < 0");
+        if (!(d.dt == d.dt) || std::isinf(d.dt)) return fail(RG_EINVAL, "dt is not finite");
+        a.dt = d.dt;
+        a.n_steps = d.n_steps;
+        if (d.store_every < 0 || d.checkpoint_every < 0) return fail(RG_EINVAL, "negative store/checkpoint interval");
+        if (d.store_every > 0) {
+            size_t ns = (size_t)d.n_steps / d.store_every + 1;
+            RGCHK(check_dev(d.traj, 8 * ns * ny * n, "traj"));
+            if (d.traj_D) RGCHK(check_dev(d.traj_D, 8 * ns * n, "traj_D"));
+            a.store_every = d.store_every;
+            a.traj = d.traj;
+            a.traj_D = d.traj_D;
+        }
+        if (d.checkpoint_every > 0) {
+            size_t nc = ((size_t)d.n_steps + d.checkpoint_every - 1) / d.checkpoint_every;
+            RGCHK(check_dev(d.checkpoints, 8 * nc * (ny + 1) * n, "checkpoints"));
+            a.ckpt_every = d.checkpoint_every;
+            a.ckpt = d.checkpoints;
+        }
+    } else {
+        if (d.store_every != 0 || d.checkpoint_every != 0)
+            return fail(RG_EUNSUPPORTED, "snapshots and checkpoints are RK4-only");
+        if (!(d.h0 > 0.0) || !(d.rtol >= 0.0) || !(d.atol >= 0.0) || !(d.rtol + d.atol > 0.0))
+            return fail(RG_EINVAL, "DOPRI54 needs h0 > 0 and rtol + atol > 0");
+        if (d.budget) RGCHK(check_dev(d.budget, 4 * n, "budget"));
+        a.budget = d.budget;
+        a.max_steps = d.max_steps;
+        a.h0 = d.h0; a.rtol = d.rtol; a.atol = d.atol; a.hmin = d.hmin; a.t_end = d.t_end;
+    }
+    return RG_OK;
+}
+
+// -------------------------------------------------------------- autotune --
+
+static std::string tune_file() {
+    const char *e = std::getenv("RAYGRAPH_TUNE_CACHE");
+    return e ? std::string(e) : std::string();
+}
+
+static void tune_load(rg_program *p) {
+    std::string f = tune_file();
+    if (f.empty()) return;
+    std::ifstream in(f);
+    std::string key;
+    TuneEntry t;
+    while (in >> key >> t.block >> t.rpl >> t.compact) p->tune[key] = t;
+}
+
+static void tune_save(const std::string &key, const TuneEntry &t) {
+    std::string f = tune_file();
+    if (f.empty()) return;
+    std::ofstream out(f, std::ios::app);
+    out << key << " " << t.block << " " << t.rpl << " " << t.compact << "\n";
+}
+
+static rg_status time_seq(rg_program *p, const std::vector<Launch> &seq, hipStream_t s, float *ms) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    RGCHK(run_seq(p, seq, false, s));  // warm
+    HIPCHK(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 2; rep++) RGCHK(run_seq(p, seq, false, s));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return RG_OK;
+}
+
+static std::string tune_key(rg_program *p, const char *what, long long n) {
+    int lg = 0;
+    while ((1ll << (lg + 1)) <= n) lg++;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%016llx|%s|n2^%d|cu%d|gfx950", (unsigned long long)p->hash, what, lg, p->n_cu);
+    return buf;
+}
+
+static rg_status persistent_rk4_seq(rg_program *p, const rg_kargs &a, int block, int rpl,
+                                    std::vector<Launch> &seq) {
+    const char *name = rpl == 2 ? "rg_rk4_r2" : "rg_rk4_r1";
+    unsigned grid;
+    RGCHK(occupancy_grid(p, name, block, (long long)cdiv(a.n_run, (long long)block * rpl), &grid));
+    seq.push_back(Launch{name, grid, (unsigned)block, a});
+    p->last.grid = (int)grid;
+    return RG_OK;
+}
+
+static rg_status dopri_seq(rg_program *p, rg_kargs a, int block, int compact, std::vector<Launch> &seq) {
+    Carve c{(char *)p->ws};
+    a.queue = c.take<unsigned long long>(1);
+    a.compact = compact;
+    rg_kargs f;
+    std::memset(&f, 0, sizeof f);
+    f.fill_p = (double *)a.queue;
+    f.fill_n = 1;
+    f.fill_v = 0.0;
+    seq.push_back(Launch{"rg_fill_f64", 1, 64, f});
+    unsigned grid;
+    RGCHK(occupancy_grid(p, "rg_dopri_persistent", block, (long long)cdiv(a.n_run, block), &grid));
+    seq.push_back(Launch{"rg_dopri_persistent", grid, (unsigned)block, a});
+    p->last.grid = (int)grid;
+    return RG_OK;
+}
+
+static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneEntry *out) {
+    std::string key = tune_key(p, "rk4", a.n);
+    if (p->tune.empty()) tune_load(p);
+    auto it = p->tune.find(key);
+    if (it != p->tune.end()) { *out = it->second; p->last.tuned = 1; return RG_OK; }
+    rg_kargs t = a;
+    t.n_steps = std::min(a.n_steps, 16);
+    t.store_every = 0;
+    t.traj = nullptr;
+    t.traj_D = nullptr;
+    t.ckpt_every = 0;
+    t.ckpt = nullptr;
+    float best = 1e30f;
+    TuneEntry bt;
+    for (int rpl : {1, 2})
+        for (int block : {64, 128, 256, 512}) {
+            std::vector<Launch> seq;
+            RGCHK(persistent_rk4_seq(p, t, block, rpl, seq));
+            float ms;
+            RGCHK(time_seq(p, seq, s, &ms));
+            if (ms < best) { best = ms; bt.block = block; bt.rpl = rpl; }
+        }
+    p->tune[key] = bt;
+    tune_save(key, bt);
+    *out = bt;
+    p->last.tuned = 1;
+    return RG_OK;
+}
+
+static rg_status tune_dopri(rg_program *p, const rg_kargs &a, hipStream_t s, TuneEntry *out) {
+    std::string key = tune_key(p, "dopri", a.n);
+    if (p->tune.empty()) tune_load(p);
+    auto it = p->tune.find(key);
+    if (it != p->tune.end()) { *out = it->second; p->last.tuned = 1; return RG_OK; }
+    rg_kargs t = a;
+    t.n_run = std::min<long long>(a.n, std::max<long long>(65536, a.n / 16));
+    t.budget_cap = 400;
+    float best = 1e30f;
+    TuneEntry bt;
+    for (int block : {64, 128, 256})
+        for (int C : {8, 32, 128, -1}) {
+            std::vector<Launch> seq;
+            RGCHK(dopri_seq(p, t, block, C, seq));
+            float ms;
+            RGCHK(time_seq(p, seq, s, &ms));
+            if (ms < best) { best = ms; bt.block = block; bt.compact = C; }
+        }
+    p->tune[key] = bt;
+    tune_save(key, bt);
+    *out = bt;
+    p->last.tuned = 1;
+    return RG_OK;
+}
+
+// ----------------------------------------------------------------- trace --
+
+rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    rg_kargs a;
+    RGCHK(validate(p, d, a));
+    if (d.n_rays == 0) return RG_OK;
+    const long long n = a.n;
+    const uint32_t ny = 2 * p->dim;
+    p->last = rg_launch_info{};
+    p->last.struct_size = sizeof(rg_launch_info);
+    const bool graph = d.use_hipgraph != 0;
+
+    if (d.integrator == RG_RK4 && d.mode == RG_PERSISTENT) {
+        TuneEntry te;
+        if (d.block == 0 || d.rays_per_lane == 0) RGCHK(tune_rk4(p, a, s, &te));
+        int block = d.block ? d.block : te.block;
+        int rpl = d.rays_per_lane ? d.rays_per_lane : te.rpl;
+        std::vector<Launch> seq;
+        RGCHK(persistent_rk4_seq(p, a, block, rpl, seq));
+        p->last.block = block;
+        p->last.rays_per_lane = rpl;
+        return run_seq(p, seq, graph, s);
+    }
+    if (d.integrator == RG_RK4) {  // plain: one launch per step
+        int block = d.block ? d.block : 256;
+        RGCHK(ensure_ws(p, 3 * 256 + 16 * (size_t)n + 256));
+        Carve c{(char *)p->ws};
+        a.s_t = c.take<double>(n);
+        a.s_st = c.take<int>(n);
+        a.s_acc = c.take<int>(n);
+        std::vector<Launch> seq;
+        unsigned grid = cdiv(n, block);
+        seq.push_back(Launch{"rg_rk4_plain_init", grid, (unsigned)block, a});
+        for (int st = 0; st < d.n_steps; st++) {
+            rg_kargs b = a;
+            b.step = st;
+            b.snap = (a.store_every > 0 && (st + 1) % a.store_every == 0) ? (st + 1) / a.store_every : -1;
+            b.ckpt_idx = (a.ckpt_every > 0 && st % a.ckpt_every == 0) ? st / a.ckpt_every : -1;
+            seq.push_back(Launch{"rg_rk4_plain_step", grid, (unsigned)block, b});
+        }
+        seq.push_back(Launch{"rg_plain_finish", grid, (unsigned)block, a});
+        p->last.block = block;
+        p->last.rays_per_lane = 1;
+        p->last.grid = (int)grid;
+        return run_seq(p, seq, graph, s);
+    }
+    if (d.mode == RG_PERSISTENT) {
+        RGCHK(ensure_ws(p, 4096));
+        TuneEntry te;
+        if (d.block == 0 || d.compact_interval == 0) RGCHK(tune_dopri(p, a, s, &te));
+        int block = d.block ? d.block : te.block;
+        int C = d.compact_interval ? d.compact_interval : te.compact;
+        std::vector<Launch> seq;
+        RGCHK(dopri_seq(p, a, block, C, seq));
+        p->last.block = block;
+        p->last.rays_per_lane = 1;
+        p->last.compact_interval = C;
+        return run_seq(p, seq, graph, s);
+    }
+    // plain adaptive: one attempt per launch, alive count read back every 64 launches
+    int block = d.block ? d.block : 256;
+    size_t need = 8 * 256 + (size_t)n * (16 * ny + 3 * 8 + 3 * 4) + 64;
+    RGCHK(ensure_ws(p, need));
+    Carve c{(char *)p->ws};
+    a.s_y = c.take<double>(ny * n);
+    a.s_k1 = c.take<double>(ny * n);
+    a.s_t = c.take<double>(n);
+    a.s_h = c.take<double>(n);
+    a.s_fm = c.take<double>(n);
+    a.s_st = c.take<int>(n);
+    a.s_acc = c.take<int>(n);
+    a.s_att = c.take<int>(n);
+    a.counter = c.take<int>(2);
+    unsigned grid = cdiv(n, block);
+    RGCHK(launch_one(p, Launch{"rg_dopri_plain_init", grid, (unsigned)block, a}, s));
+    long long maxb = d.max_steps;
+    if (d.budget) {
+        std::vector<int> hb(n);
+        HIPCHK(hipMemcpyAsync(hb.data(), d.budget, 4 * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        maxb = *std::max_element(hb.begin(), hb.end());
+    }
+    const long long cap = 4 * std::max<long long>(maxb, 1) + 128;
+    int *host = nullptr;
+    HIPCHK(hipHostMalloc((void **)&host, 8, 0));
+    rg_status st = RG_OK;
+    for (long long it = 0; it < cap; it++) {
+        const bool check = (it % 64) == 63;
+        rg_kargs b = a;
+        b.count_alive = check ? 1 : 0;
+        if (check) {
+            rg_kargs f;
+            std::memset(&f, 0, sizeof f);
+            f.fill_p = (double *)a.counter;
+            f.fill_n = 1;
+            f.fill_v = 0.0;
+            if ((st = launch_one(p, Launch{"rg_fill_f64", 1, 64, f}, s)) != RG_OK) break;
+        }
+        if ((st = launch_one(p, Launch{"rg_dopri_plain_step", grid, (unsigned)block, b}, s)) != RG_OK) break;
+        if (check) {
+            hipError_t e = hipMemcpyAsync(host, a.counter, 4, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { st = fail(RG_EHIP, std::string("plain DOPRI readback: ") + hipGetErrorString(e)); break; }
+            if (host[0] == 0) break;
+        }
+    }
+    (void)hipHostFree(host);
+    p->last.block = block;
+    p->last.rays_per_lane = 1;
+    p->last.grid = (int)grid;
+    return st;
+}
+
+// --------------------------------------------------------------- adjoint --
+
+rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    if (!p->has_vjp) return fail(RG_ESTATE, "program compiled without want_adjoint");
+    if (ad.struct_size < sizeof(rg_adjoint_desc)) return fail(RG_EINVAL, "rg_adjoint_desc.struct_size too small");
+    if (!ad.fwd) return fail(RG_EINVAL, "adjoint needs the forward description");
+    const rg_trace_desc &d = *ad.fwd;
+    if (d.integrator != RG_RK4) return fail(RG_EUNSUPPORTED, "adjoint is implemented for RK4");
+    if (d.checkpoint_every <= 0 || !d.checkpoints || !d.steps_out)
+        return fail(RG_ESTATE, "adjoint needs the forward checkpoints and steps_out");
+    rg_kargs a;
+    RGCHK(validate(p, d, a));
+    if (d.n_rays == 0) return RG_OK;
+    const long long n = a.n;
+    const uint32_t dim = p->dim, ny = 2 * dim;
+    RGCHK(check_dev(ad.dL_dx_end, 8 * dim * n, "dL_dx_end"));
+    if (ad.dL_dk_end) RGCHK(check_dev(ad.dL_dk_end, 8 * dim * n, "dL_dk_end"));
+    if (ad.dL_dx0) RGCHK(check_dev(ad.dL_dx0, 8 * dim * n, "dL_dx0"));
+    if (ad.dL_dk0) RGCHK(check_dev(ad.dL_dk0, 8 * dim * n, "dL_dk0"));
+    for (uint32_t i = 0; i < p->n_params; i++)
+        if (ad.dL_dparams && ad.dL_dparams[i]) {
+            RGCHK(check_dev(ad.dL_dparams[i], 8 * (size_t)p->param_len[i], "dL_dparams[i]"));
+            a.dparams[i] = ad.dL_dparams[i];
+        }
+    a.lam_x = ad.dL_dx_end;
+    a.lam_k = ad.dL_dk_end;
+    a.gx0 = ad.dL_dx0;
+    a.gk0 = ad.dL_dk0;
+
+    const int block = d.block ? d.block : 256;
+    unsigned grid;
+    RGCHK(occupancy_grid(p, "rg_rk4_adjoint", block, (long long)cdiv(n, block), &grid));
+    const long long lanes = (long long)grid * block;
+    const int stride = (int)(p->grad_param.size() + (size_t)p->spl_total);
+    const size_t scratch = (size_t)d.checkpoint_every * (ny + 1) * lanes;
+    const size_t gpart = (size_t)grid * stride;
+    RGCHK(ensure_ws(p, 8 * (scratch + gpart) + 1024));
+    Carve c{(char *)p->ws};
+    a.scratch = c.take<double>(scratch);
+    a.gpart = stride > 0 ? c.take<double>(gpart) : nullptr;
+    a.scratch_lanes = lanes;
+    a.n_part = (int)grid;
+    a.part_stride = stride;
+
+    // zero the parameter gradients that will be written
+    for (uint32_t i = 0; i < p->n_params; i++)
+        if (a.dparams[i]) {
+            rg_kargs f;
+            std::memset(&f, 0, sizeof f);
+            f.fill_p = a.dparams[i];
+            f.fill_n = p->param_len[i];
+            f.fill_v = 0.0;
+            RGCHK(launch_one(p, Launch{"rg_fill_f64", cdiv(f.fill_n, 256), 256, f}, s));
+        }
+    RGCHK(launch_one(p, Launch{"rg_rk4_adjoint", grid, (unsigned)block, a}, s));
+    if (stride > 0) RGCHK(launch_one(p, Launch{"rg_grad_finalize", cdiv(stride, 256), 256, a}, s));
+    p->last.block = block;
+    p->last.grid = (int)grid;
+    return RG_OK;
+}
+
+rg_status eval_points(rg_program *p, uint32_t n, const double *y, const double *omega,
+                      const double *t, const double *const *params, double *f, double *D,
+                      hipStream_t s) {
+    RGCHK(ensure_module(p));
+    if (n == 0) return RG_OK;
+    const uint32_t ny = 2 * p->dim;
+    rg_kargs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = n;
+    a.n_run = n;
+    RGCHK(check_dev(y, 8 * (size_t)ny * n, "y"));
+    RGCHK(check_dev(omega, 8 * (size_t)n, "omega"));
+    if (t) RGCHK(check_dev(t, 8 * (size_t)n, "t"));
+    if (f) RGCHK(check_dev(f, 8 * (size_t)ny * n, "f_out"));
+    if (D) RGCHK(check_dev(D, 8 * (size_t)n, "D_out"));
+    if (p->n_params > 0 && !params) return fail(RG_EINVAL, "params is NULL but the graph has parameters");
+    for (uint32_t i = 0; i < p->n_params; i++) {
+        RGCHK(check_dev(params[i], 8 * (size_t)p->param_len[i], "params[i]"));
+        a.params[i] = params[i];
+    }
+    a.x0 = y;
+    a.omega = omega;
+    a.t0 = t;
+    a.x_out = f;
+    a.t_out = D;
+    return launch_one(p, Launch{"rg_eval_points", cdiv(n, 256), 256, a}, s);
+}
+
+}  // namespace rg

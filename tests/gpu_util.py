@@ -1,0 +1,91 @@
+"""Shared helpers for the GPU parity tests: compile a workload's medium once,
+move seeded inputs to the GPU, run the C-ABI trace, and compare with the
+oracle using the per-ray norms fixed for this build:
+
+  e_x = |x_gpu - x_ora| / max(|x_ora|, 1)
+  e_k = |k_gpu - k_ora| / max(|k_ora|, 0.1 omega)
+
+(component-wise relative error is undefined where a component is 0).
+"""
+import numpy as np
+
+TOL = 1e-11  # positions and wavevectors, relative (per ray, as above)
+
+_progs = {}
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def program(w, want_adjoint=False):
+    from paper_2508_15967_amd import media
+    key = (w.cfg, w.name, want_adjoint, id(w.medium) if w.cfg in ("h", "o", "l") else 0)
+    if key not in _progs:
+        g, D, params = media.build(w.medium)
+        prog = g.compile(D, want_adjoint=want_adjoint)
+        _progs[key] = (g, D, prog, params)
+    return _progs[key]
+
+
+def dev(a, dtype=None):
+    torch = torch_mod()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def gpu_trace(w, store=False, store_D=False, checkpoint_every=0, **kw):
+    """Trace workload w on the GPU through the C ABI; returns numpy arrays
+    (and the torch tensors under '_t')."""
+    torch = torch_mod()
+    _, _, prog, params = program(w, want_adjoint=kw.pop("want_adjoint", False))
+    x0, k0, om = dev(w.x0), dev(w.k0), dev(w.omega)
+    pt = [dev(p) for p in params]
+    args = dict(integrator=w.integrator, dt=w.dt, n_steps=w.n_steps, h0=w.h0, rtol=w.rtol,
+                atol=w.atol, hmin=w.hmin)
+    if w.budget is not None:
+        args["budget"] = dev(w.budget.astype(np.int32))
+    if w.box_lo is not None:
+        args["box"] = (list(w.box_lo), list(w.box_hi))
+    if store or store_D:
+        args["store_every"] = w.store_every
+    args.update(kw)
+    out = prog.trace(x0, k0, om, pt, store=store, store_D=store_D,
+                     checkpoint_every=checkpoint_every, **args)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "_desc"}
+    res["_t"] = out
+    res["_in"] = (x0, k0, om, pt)
+    return res
+
+
+def ray_errors(go, oo, omega, dim):
+    """Per-ray relative errors of positions and wavevectors."""
+    ex = np.linalg.norm(go["x"] - oo["x"], axis=0) / np.maximum(np.linalg.norm(oo["x"], axis=0), 1.0)
+    ek = np.linalg.norm(go["k"] - oo["k"], axis=0) / np.maximum(np.linalg.norm(oo["k"], axis=0), 0.1 * omega)
+    return ex, ek
+
+
+def traj_errors(tg, to, omega, dim):
+    """Max over snapshots of the per-ray relative errors; traj [snap][2d][n]."""
+    dx = np.linalg.norm(tg[:, :dim] - to[:, :dim], axis=1)
+    dk = np.linalg.norm(tg[:, dim:] - to[:, dim:], axis=1)
+    nx = np.maximum(np.linalg.norm(to[:, :dim], axis=1), 1.0)
+    nk = np.maximum(np.linalg.norm(to[:, dim:], axis=1), 0.1 * omega[None, :])
+    return (dx / nx).max(), (dk / nk).max()
+
+
+def ill_conditioned(oracle, w, thr=1e-12):
+    """Rays whose oracle trajectory moves by more than thr (relative) when
+    the last bit of the initial state is flipped: rounding differences are
+    amplified there, so they are compared by one-step parity instead."""
+    base = oracle.trace(w)
+    w2 = w.subset(w.n)
+    w2.x0 = np.nextafter(w.x0, np.inf)
+    w2.k0 = np.nextafter(w.k0, np.inf)
+    pert = oracle.trace(w2)
+    ex, ek = ray_errors(pert, base, w.omega, w.dim)
+    return np.maximum(ex, ek) > thr, base

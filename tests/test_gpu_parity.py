@@ -1,0 +1,127 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Tolerance 1e-11 relative per ray on positions and
+wavevectors (see gpu_util for the norms); t bitwise for fixed-step RK4."""
+import numpy as np
+import pytest
+
+from paper_2508_15967_amd import workloads as W
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _print_case(name, w):
+    print(f"[case] {name} cfg={w.cfg} n={w.n} steps={w.n_steps}", flush=True)
+
+
+@pytest.mark.parametrize("cfg", ["1", "2", "3", "4", "5"])
+def test_rhs_points_match_oracle(oracle, cfg):
+    """Emitted right-hand side and D on the GPU vs the hand-derived oracle."""
+    w = W.make(cfg, 2048)
+    _print_case("rhs", w)
+    torch = U.torch_mod()
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, w.n, 2048)
+    y = np.concatenate([w.x0[:, idx] + rng.uniform(-1, 1, (w.dim, 2048)),
+                        w.k0[:, idx] * (1 + 0.05 * rng.uniform(-1, 1, (1, 2048)))])
+    om = w.omega[idx]
+    _, _, prog, params = U.program(w)
+    f, D = prog.eval(U.dev(y), U.dev(om), [U.dev(p) for p in params])
+    torch.cuda.synchronize()
+    fo, Do, _ = oracle.eval_points(w.medium, y, om)
+    scale = np.abs(fo).max(axis=0) + 1e-300
+    assert (np.abs(f.cpu().numpy() - fo).max(axis=0) / scale).max() < 1e-13
+    assert np.abs(D.cpu().numpy() - Do).max() < 1e-13 * (1 + np.abs(Do).max())
+
+
+def test_lens_full_trajectories(oracle):
+    """Workload 1 as specified: 1,024 rays, 1,000 steps, every state stored."""
+    w = W.make("1")
+    _print_case("lens", w)
+    g = U.gpu_trace(w, store=True, store_D=True)
+    o = oracle.trace(w, store=True, store_D=True)
+    ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    assert np.array_equal(g["t"], o["t"])
+    assert np.array_equal(g["status"], o["status"]) and np.array_equal(g["steps"], o["steps"])
+    assert np.abs(g["traj_D"] - o["traj_D"]).max() < 1e-13
+
+
+def test_lens_long_crosses_lens(oracle):
+    w = W.make("1b")
+    _print_case("lens_long", w)
+    g = U.gpu_trace(w, store=True)
+    o = oracle.trace(w, store=True)
+    ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    # the lens deflects the rays: k_y is no longer zero
+    assert np.abs(o["k"][1]).max() > 0.05
+
+
+def test_stratified_subset(oracle):
+    w = W.make("2", 4096)
+    _print_case("strat", w)
+    g = U.gpu_trace(w, store=True)
+    o = oracle.trace(w, store=True)
+    ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    # k_parallel conserved bitwise on the GPU too (dk_x/dt = dk_y/dt = 0)
+    assert np.array_equal(g["k"][:2], w.k0[:2])
+    assert np.array_equal(g["t"], o["t"])
+
+
+def test_stratified_full_size_sampled(oracle):
+    """Full workload 2 (1,048,576 rays, 10,000 steps, 101 snapshots) in the
+    benchmark's launch configuration; 192 sampled rays recomputed by the oracle."""
+    w = W.make("2")
+    _print_case("strat_full", w)
+    torch = U.torch_mod()
+    g = U.gpu_trace(w, store=True)
+    rng = np.random.default_rng(99)
+    idx = np.sort(rng.choice(w.n, 192, replace=False))
+    ws = w.subset(w.n)
+    ws.x0, ws.k0, ws.omega = w.x0[:, idx].copy(), w.k0[:, idx].copy(), w.omega[idx].copy()
+    o = oracle.trace(ws, store=True)
+    ex, ek = U.traj_errors(g["traj"][:, :, idx], o["traj"], ws.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    assert np.all(g["status"] == 0) and np.all(g["steps"] == w.n_steps)
+    del g
+    torch.cuda.empty_cache()
+
+
+def test_spline_forward(oracle):
+    w = W.make("4", 2048)
+    w.n_steps = 2000
+    _print_case("spline", w)
+    g = U.gpu_trace(w)
+    o = oracle.trace(w)
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
+
+
+def test_aniso_forward(oracle):
+    w = W.make("5", 1024)
+    w.n_steps = 2000
+    _print_case("aniso", w)
+    g = U.gpu_trace(w)
+    bad, o = U.ill_conditioned(oracle, w)
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    ok = ~bad
+    print(f"ill-conditioned rays excluded: {bad.sum()} of {w.n}")
+    assert bad.mean() < 0.05
+    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+
+
+def test_dopri_bumps_subset(oracle):
+    """Adaptive Dormand-Prince with box and budget termination: statuses and
+    accepted-step counts identical, endpoints within tolerance."""
+    w = W.make("3", 8192)
+    _print_case("dopri", w)
+    g = U.gpu_trace(w)
+    bad, o = U.ill_conditioned(oracle, w)
+    same = (g["status"] == o["status"]) & (g["steps"] == o["steps"])
+    print(f"ill-conditioned: {bad.sum()}, status/steps mismatches: {(~same).sum()}")
+    assert same.mean() >= 0.999
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    ok = same & ~bad
+    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
