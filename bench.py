@@ -40,6 +40,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--traffic", default="", help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--block", type=int, default=0, help="fix the block size (0 = autotuned)")
+    ap.add_argument("--rpl", type=int, default=0, help="fix rays per lane (0 = autotuned)")
+    ap.add_argument("--compact", type=int, default=0, help="fix the compaction interval (0 = autotuned)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     return ap.parse_args()
 
 
@@ -89,7 +95,15 @@ def main():
     stream = torch.cuda.current_stream()
 
     def make(mode):
-        return prog.make_desc(x0, k0, om, pt, mode=mode, use_hipgraph=True, **kw, **outs)
+        return prog.make_desc(x0, k0, om, pt, mode=mode, use_hipgraph=True, block=args.block,
+                              rays_per_lane=args.rpl, compact_interval=args.compact, **kw, **outs)
+
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     desc = make(rgb.PERSISTENT)
     adj = {}
@@ -208,24 +222,33 @@ def main():
                            "launches_per_trace": w.n_steps + 2 if w.integrator == W.RK4 else None}
         result["speedup_vs_plain"] = (ray_steps / (ms_per_step * 1e-3)) / (psteps / pw)
 
-    # CPU oracle on a bounded sample of the same workload
+    # CPU oracle on a bounded sample of the same workload: a pilot run sizes
+    # the sample to about --cpu-seconds of work on all host cores
     if not args.no_cpu:
         from oracle import pyoracle
         pyoracle.build(force=False)
         cores = pyoracle.threads()
-        m = args.cpu_rays or {"1": 1024, "2": 16 * cores * 64, "3": 8 * cores * 64,
-                              "4": 2 * cores * 64, "5": cores * 8}.get(args.config, 4096)
-        ws = w.subset(min(m, w.n))
-        t0 = time.perf_counter()
-        ro = pyoracle.trace(ws)
-        if adjoint:
-            lam = np.concatenate([2 * (ro["x"] - ws.targets), np.zeros_like(ro["k"])])
-            pyoracle.adjoint(ws, lam)
-        cs = time.perf_counter() - t0
+
+        def oracle_run(m):
+            ws = w.subset(min(m, w.n))
+            t0 = time.perf_counter()
+            ro = pyoracle.trace(ws)
+            if adjoint:
+                lam = np.concatenate([2 * (ro["x"] - ws.targets), np.zeros_like(ro["k"])])
+                pyoracle.adjoint(ws, lam)
+            return ws, ro, time.perf_counter() - t0
+
+        m = args.cpu_rays
+        if not m:
+            pilot = min(w.n, 4 * cores)
+            _, _, ps = oracle_run(pilot)
+            m = int(min(w.n, max(pilot, pilot * args.cpu_seconds / max(ps, 1e-3))))
+        ws, ro, cs = oracle_run(m)
         crs = int(ro["steps"].astype(np.int64).sum())
         result["cpu_baseline"] = {"value": crs / cs, "unit": "ray-steps/s" + (" (fwd+adj)" if adjoint else ""),
                                   "cores": cores, "kind": "oracle",
-                                  "sample": f"first {ws.n} rays of {w.name}, all steps, {cs:.1f} s"}
+                                  "sample": f"first {ws.n} of {w.n} rays of {w.name}, all steps"
+                                            f"{' fwd+adj' if adjoint else ''}, {cs:.1f} s"}
     print(json.dumps(result))
 
 

@@ -1,0 +1,173 @@
+"""GPU adjoint (checkpointed discrete RK4 adjoint through the C ABI) against
+the oracle's discrete adjoint and tangent-linear derivatives and against
+central finite differences of the GPU forward.
+
+Loss: L = sum_r |x_end,r - target_r|^2, so dL/dx_end = 2 (x_end - target),
+dL/dk_end = 0.  Gradients with respect to k0 (per ray) and the medium
+parameters (spline coefficients / blob scales, summed over rays).
+"""
+import numpy as np
+import pytest
+
+from paper_2508_15967_amd import workloads as W
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+ORACLE_TOL = 1e-9   # GPU adjoint vs oracle adjoint / tangent-linear
+FD_TOL = 1e-6       # GPU adjoint vs central differences, h = 1e-6
+
+
+def _gpu_grad(w, ckpt=100):
+    torch = U.torch_mod()
+    _, _, prog, params = U.program(w, want_adjoint=True)
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    pt = [U.dev(p) for p in params]
+    out = prog.trace(x0, k0, om, pt, dt=w.dt, n_steps=w.n_steps, checkpoint_every=ckpt)
+    tgt = U.dev(w.targets)
+    lx = (2.0 * (out["x"] - tgt)).contiguous()
+    gx0 = torch.empty_like(x0)
+    gk0 = torch.empty_like(k0)
+    gp = [torch.empty_like(p) for p in pt]
+    prog.adjoint_desc(out["_desc"], lx, None, gx0, gk0, gp)
+    torch.cuda.synchronize()
+    return {"x": out["x"].cpu().numpy(), "gx0": gx0.cpu().numpy(), "gk0": gk0.cpu().numpy(),
+            "gp": [g.cpu().numpy() for g in gp], "prog": prog, "pt": pt, "in": (x0, k0, om)}
+
+
+def _per_ray_loss(prog, x0, k0, om, pt, w):
+    torch = U.torch_mod()
+    out = prog.trace(x0, k0, om, pt, dt=w.dt, n_steps=w.n_steps, block=256, rays_per_lane=1)
+    torch.cuda.synchronize()
+    d = out["x"].cpu().numpy() - w.targets
+    return (d * d).sum(0)
+
+
+def _fd(loss_fn, set_fn, orig, h=1e-6):
+    """Per-ray-summed central difference at h and 2h.  Their difference
+    estimates the rounding noise of the quotient (truncation is O(h^2))."""
+    out = []
+    for hh in (h, 2 * h):
+        set_fn(orig + hh)
+        lp = loss_fn()
+        set_fn(orig - hh)
+        lm = loss_fn()
+        out.append(((lp - lm) / (2 * hh)).sum())
+    set_fn(orig)
+    return out[0], abs(out[0] - out[1])
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("cfg,n,steps", [("4", 2048, 1000), ("5", 512, 1000)])
+def test_adjoint_matches_oracle_adjoint(oracle, cfg, n, steps):
+    w = W.make(cfg, n)
+    w.n_steps = steps
+    print(f"[case] adjoint-vs-oracle cfg={cfg} n={n} steps={steps}", flush=True)
+    g = _gpu_grad(w)
+    o = oracle.trace(w)
+    lam = np.concatenate([2 * (o["x"] - w.targets), np.zeros_like(o["k"])])
+    lam0, go = oracle.adjoint(w, lam)
+    assert _rel(g["gk0"], lam0[w.dim:]) < ORACLE_TOL
+    assert _rel(g["gx0"], lam0[: w.dim]) < ORACLE_TOL
+    assert _rel(g["gp"][0], go) < ORACLE_TOL, _rel(g["gp"][0], go)
+
+
+@pytest.mark.parametrize("cfg,n,steps", [("4", 1024, 600), ("5", 256, 600)])
+def test_adjoint_matches_tangent_linear(oracle, cfg, n, steps):
+    """Directional derivatives from the oracle's forward-mode pass (no reverse
+    code involved) for 4 parameters and a random k0 direction."""
+    w = W.make(cfg, n)
+    w.n_steps = steps
+    g = _gpu_grad(w)
+    o = oracle.trace(w)
+    lam = np.concatenate([2 * (o["x"] - w.targets), np.zeros_like(o["k"])])
+    n2 = 2 * w.dim
+    for p in [int(v) for v in w.fd_params[:4]]:
+        dy = oracle.tangent(w, np.zeros((n2, w.n)), p=p)
+        ref = (lam * dy).sum()
+        assert abs(g["gp"][0][p] - ref) <= ORACLE_TOL * max(abs(ref), 1e-3), (p, g["gp"][0][p], ref)
+    rng = np.random.default_rng(5)
+    dk = rng.standard_normal((w.dim, w.n))
+    dy = oracle.tangent(w, np.concatenate([np.zeros((w.dim, w.n)), dk]))
+    ref = (lam * dy).sum()
+    got = (g["gk0"] * dk).sum()
+    assert abs(got - ref) <= ORACLE_TOL * abs(ref)
+
+
+def test_spline_adjoint_full_size_vs_fd():
+    """Workload 4 at full size (65,536 rays x 5,000 steps, checkpoints every
+    100): the 32 drawn coefficients and 16 k0 entries against per-ray-summed
+    central differences of the GPU forward (h = 1e-6)."""
+    torch = U.torch_mod()
+    w = W.make("4")
+    print("[case] spline adjoint full size vs FD", flush=True)
+    g = _gpu_grad(w)
+    prog, pt = g["prog"], g["pt"]
+    x0, k0, om = g["in"]
+    coef = pt[0]
+    loss = lambda: _per_ray_loss(prog, x0, k0, om, pt, w)
+    checked = 0
+    for p in [int(v) for v in w.fd_params]:
+        def setc(v, p=p):
+            coef[p] = v
+        fd, noise = _fd(loss, setc, coef[p].item())
+        ad = g["gp"][0][p]
+        print(f"coef {p}: adjoint {ad:.12e} fd {fd:.12e} noise {noise:.1e}")
+        assert abs(ad - fd) <= FD_TOL * abs(fd) + 3 * noise, (p, ad, fd, noise)
+        checked += noise < 1e-7 * abs(fd)
+    assert checked >= 24
+    rng = np.random.default_rng(8)
+    for r in rng.choice(w.n, 8, replace=False):
+        for c in range(2):
+            kp = k0.clone()
+            def setk(v, c=c, r=r):
+                kp[c, r] = v
+            fd, noise = _fd(lambda r=r: _per_ray_loss(prog, x0, kp, om, pt, w)[r:r + 1], setk,
+                            k0[c, r].item())
+            assert abs(g["gk0"][c, r] - fd) <= FD_TOL * abs(fd) + 3 * noise, (r, c, g["gk0"][c, r], fd)
+    torch.cuda.empty_cache()
+
+
+def test_aniso_adjoint_scales_vs_fd():
+    """Workload 5 medium (16 blob scales) on 16,384 rays x 4,000 steps: all 16
+    scale gradients against central differences of the GPU forward."""
+    w = W.make("5", 16384)
+    w.n_steps = 4000
+    print("[case] aniso adjoint vs FD", flush=True)
+    g = _gpu_grad(w)
+    prog, pt = g["prog"], g["pt"]
+    x0, k0, om = g["in"]
+    s = pt[0]
+    loss = lambda: _per_ray_loss(prog, x0, k0, om, pt, w)
+    checked = 0
+    for p in range(16):
+        def sets(v, p=p):
+            s[p] = v
+        fd, noise = _fd(loss, sets, s[p].item())
+        ad = g["gp"][0][p]
+        print(f"scale {p}: adjoint {ad:.12e} fd {fd:.12e} noise {noise:.1e}")
+        assert abs(ad - fd) <= FD_TOL * abs(fd) + 3 * noise, (p, ad, fd, noise)
+        checked += noise < 1e-7 * abs(fd)
+    assert checked >= 8
+
+
+def test_autograd_function_matches_adjoint():
+    """RayTrace (torch.autograd.Function) gives the same gradients as the
+    direct adjoint call, with the loss written in torch."""
+    import torch
+    from paper_2508_15967_amd.autograd import RayTracer
+    w = W.make("4", 1024)
+    w.n_steps = 500
+    g = _gpu_grad(w)
+    tracer = RayTracer(w.medium, dt=w.dt, n_steps=w.n_steps, checkpoint_every=100)
+    x0, k0, om = g["in"]
+    k0r = k0.clone().requires_grad_(True)
+    coef = g["pt"][0].clone().requires_grad_(True)
+    x_end, k_end = tracer(x0, k0r, om, coef)
+    loss = ((x_end - U.dev(w.targets)) ** 2).sum()
+    loss.backward()
+    assert np.allclose(k0r.grad.cpu().numpy(), g["gk0"], rtol=0, atol=1e-13)
+    assert np.allclose(coef.grad.cpu().numpy(), g["gp"][0], rtol=1e-12, atol=1e-13)

@@ -1,0 +1,145 @@
+"""Launch-shape invariance and boundary behaviour on the GPU.
+
+Each ray's arithmetic does not depend on which lane, wave or launch runs
+it, so every tuning variant (block size, rays per lane, compaction
+interval), the plain one-launch-per-step form, hipGraph replay and a trace
+split in two and resumed must give bitwise-identical results."""
+import numpy as np
+import pytest
+
+from paper_2508_15967_amd import raygraph as rgb
+from paper_2508_15967_amd import workloads as W
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(a, b, keys=("x", "k", "t", "status", "steps")):
+    for k in keys:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_rk4_variants_bitwise():
+    w = W.make("2", 5000)  # ragged: not a multiple of any block size
+    w.n_steps = 400
+    base = U.gpu_trace(w, block=256, rays_per_lane=1, store=True)
+    for block in (64, 128, 512):
+        for rpl in (1, 2):
+            print(f"[case] rk4 block={block} rpl={rpl}", flush=True)
+            _same(base, U.gpu_trace(w, block=block, rays_per_lane=rpl, store=True), ("x", "k", "t", "traj"))
+    pl = U.gpu_trace(w, mode=rgb.PLAIN, block=128, store=True)
+    _same(base, pl, ("x", "k", "t", "status", "steps", "traj"))
+    gr = U.gpu_trace(w, block=256, rays_per_lane=2, use_hipgraph=True, store=True)
+    _same(base, gr, ("x", "k", "traj"))
+    gr2 = U.gpu_trace(w, block=256, rays_per_lane=2, use_hipgraph=True, store=True)  # replay
+    _same(base, gr2, ("x", "k", "traj"))
+
+
+def test_rk4_autotuned_matches_fixed():
+    w = W.make("1b", 1000)
+    w.n_steps = 300
+    a = U.gpu_trace(w)
+    b = U.gpu_trace(w, block=64, rays_per_lane=1)
+    _same(a, b)
+
+
+def test_split_and_resume_bitwise():
+    w = W.make("4", 3000)
+    w.n_steps = 600
+    full = U.gpu_trace(w, block=128, rays_per_lane=1)
+    w1 = w.subset(w.n)
+    w1.n_steps = 250
+    a = U.gpu_trace(w1, block=128, rays_per_lane=1)
+    w2 = w.subset(w.n)
+    w2.x0, w2.k0 = a["x"], a["k"]
+    w2.n_steps = 350
+    b = U.gpu_trace(w2, block=128, rays_per_lane=1, t0=U.dev(a["t"]))
+    assert np.array_equal(full["x"], b["x"]) and np.array_equal(full["k"], b["k"])
+    assert np.array_equal(full["t"], b["t"])
+
+
+def test_dopri_variants_bitwise():
+    w = W.make("3", 6000)
+    base = U.gpu_trace(w, block=128, compact_interval=32)
+    for block, C in ((64, 8), (256, 128), (128, -1), (512, 1)):
+        print(f"[case] dopri block={block} C={C}", flush=True)
+        _same(base, U.gpu_trace(w, block=block, compact_interval=C))
+    _same(base, U.gpu_trace(w, block=128, compact_interval=32, use_hipgraph=True))
+    _same(base, U.gpu_trace(w, block=128, compact_interval=32, use_hipgraph=True))
+    _same(base, U.gpu_trace(w, mode=rgb.PLAIN, block=256))
+
+
+def test_status_paths_match_oracle(oracle):
+    """Non-finite input, a start outside the box and a one-step budget give the
+    same statuses, step counts and final states as the oracle."""
+    w = W.make("3", 256)
+    w.x0 = w.x0.copy()
+    w.k0 = w.k0.copy()
+    w.budget = w.budget.copy()
+    w.x0[0, 0] = np.nan           # non-finite start
+    w.x0[2, 1] = -1.0             # below the box floor
+    w.budget[2] = 1               # one accepted step
+    w.k0[:, 3] = [np.inf, 0, 0]   # non-finite wavevector
+    g = U.gpu_trace(w, block=64, compact_interval=16)
+    o = oracle.trace(w)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["steps"], o["steps"])
+    assert g["status"][0] == rgb.RAY_NONFINITE and g["status"][3] == rgb.RAY_NONFINITE
+    assert g["status"][1] == rgb.RAY_EXITED_BOX and g["steps"][1] == 1
+    assert g["status"][2] == rgb.RAY_BUDGET and g["steps"][2] == 1
+    fin = np.isfinite(o["x"]).all(0)
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    assert ex[fin].max() < U.TOL and ek[fin].max() < U.TOL
+    # RK4 with a non-finite start freezes at the start with NONFINITE
+    w4 = W.make("1", 64)
+    w4.x0 = w4.x0.copy()
+    w4.x0[1, 5] = np.nan
+    w4.n_steps = 50
+    g4 = U.gpu_trace(w4, block=64, rays_per_lane=1)
+    o4 = oracle.trace(w4)
+    assert np.array_equal(g4["status"], o4["status"]) and g4["status"][5] == rgb.RAY_NONFINITE
+    assert np.array_equal(g4["steps"], o4["steps"])
+
+
+def test_empty_and_single_ray(oracle):
+    torch = U.torch_mod()
+    w = W.make("1", 1)
+    w.n_steps = 100
+    g = U.gpu_trace(w)
+    o = oracle.trace(w)
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    assert ex.max() < U.TOL and ek.max() < U.TOL
+    _, _, prog, _ = U.program(w)
+    e = torch.empty((2, 0), dtype=torch.float64, device="cuda")
+    d = prog.make_desc(e, e, torch.empty(0, dtype=torch.float64, device="cuda"), dt=1e-3, n_steps=10,
+                       x_out=e, k_out=e)
+    prog.trace_desc(d)  # zero rays is a no-op
+
+
+def test_boundary_rejects_bad_buffers():
+    """Host pointers and undersized device buffers are refused before any
+    launch (RG_EINVAL), with a message."""
+    torch = U.torch_mod()
+    w = W.make("1", 128)
+    _, _, prog, _ = U.program(w)
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    xo = torch.empty((2, 128), dtype=torch.float64, device="cuda")
+    ko = torch.empty((2, 128), dtype=torch.float64, device="cuda")
+    d = prog.make_desc(x0, k0, om, dt=1e-3, n_steps=10, x_out=xo, k_out=ko)
+    host = np.zeros((2, 128))
+    d.x_out = host.ctypes.data
+    with pytest.raises(rgb.RayGraphError) as e:
+        prog.trace_desc(d)
+    assert e.value.status == rgb.RG_EINVAL and "device memory" in str(e.value)
+    small = torch.empty(2 * 128 - 1, dtype=torch.float64, device="cuda")
+    # a separate allocation that is too small for 2 x 128 doubles
+    torch.cuda.empty_cache()
+    d = prog.make_desc(x0, k0, om, dt=1e-3, n_steps=10, x_out=xo, k_out=ko)
+    d.n_rays = 1 << 30  # claims far more rays than the buffers hold
+    with pytest.raises(rgb.RayGraphError) as e:
+        prog.trace_desc(d)
+    assert e.value.status == rgb.RG_EINVAL and "smaller than required" in str(e.value)
+    del small
+    d = prog.make_desc(x0, k0, om, dt=1e-3, n_steps=10, x_out=xo, k_out=ko, block=96)
+    with pytest.raises(rgb.RayGraphError):
+        prog.trace_desc(d)
