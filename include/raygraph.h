@@ -36,6 +36,9 @@
  *     synchronisation.  Per-ray numerical trouble (a non-finite state, a step
  *     underflow) is not an API error: it is reported in status_out.
  *   - C++ exceptions never cross this boundary.
+ *   - The library must use the same HIP runtime instance as the caller that
+ *     owns the streams and memory: load it after that runtime (for PyTorch,
+ *     after importing torch, which ships its own libamdhip64).
  */
 #ifndef RAYGRAPH_H
 #define RAYGRAPH_H

@@ -19,7 +19,31 @@ LIB_PATH = os.path.join(HERE, "libraygraph.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2508_15967_amd.build`")
 
+# The library must share the process's HIP runtime with the caller that owns
+# the device memory and streams (PyTorch here).  PyTorch ships its own
+# libamdhip64; loading it first lets the dynamic loader satisfy this
+# library's dependency with that same runtime instead of a second copy.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - host-only use without torch
+    pass
+
 _lib = C.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1] if len(line.split()) >= 6 else ""
+            if os.path.basename(path).startswith("libamdhip64.so"):
+                paths.add(os.path.realpath(path))
+    return sorted(paths)
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are loaded in this process (%s); import torch before "
+                      "any other HIP library so that one runtime serves both" % _hip_runtimes())
 
 # status codes and enums (raygraph.h)
 RG_OK, RG_EINVAL, RG_ENOMEM, RG_ECOMPILE, RG_EHIP, RG_EUNSUPPORTED, RG_ESTATE = 0, -1, -2, -3, -4, -5, -6

