@@ -207,6 +207,32 @@ def main():
         result["fwd_adj"]["frac_alg"] = result["fwd_adj"]["tflops_alg"] / PEAK_FP64_TFLOPS
         result["fwd_adj"]["frac_issued"] = result["fwd_adj"]["tflops_issued"] / PEAK_FP64_TFLOPS
 
+    # hand-derived-derivative kernels for the anisotropic medium (speed
+    # reference for the compiled kernels on the same inputs)
+    if args.config == "5":
+        from paper_2508_15967_amd import hand
+        hm = hand.medium_struct(w.medium)
+        hx, hk = torch.empty_like(x0), torch.empty_like(k0)
+        hcp = torch.empty_like(ckpt)
+        hgx, hgk, hgs = torch.empty_like(x0), torch.empty_like(k0), torch.empty_like(pt[0])
+        hl = torch.empty_like(x0)
+        def hand_fwd():
+            hand.trace(hm, x0, k0, om, pt[0], w.dt, w.n_steps, hx, hk, w.ckpt_every, hcp, stream=stream)
+        def hand_bwd():
+            torch.mul(hx - adj["tx"], 2.0, out=hl)
+            hand.adjoint(hm, om, pt[0], w.dt, w.n_steps, w.ckpt_every, hcp, hl, None, hgx, hgk, hgs,
+                         stream=stream)
+        hand_fwd(); hand_bwd()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream); hand_fwd(); e[1].record(stream); hand_bwd(); e[2].record(stream)
+        torch.cuda.synchronize()
+        hf, hb = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        result["hand"] = {"fwd_ms": hf, "adj_ms": hb,
+                          "fwd_ray_steps_per_s": ray_steps / (hf * 1e-3),
+                          "fwd_adj_ray_steps_per_s": ray_steps / ((hf + hb) * 1e-3),
+                          "compiled_over_hand_fwd": hf / fwd_ms,
+                          "compiled_over_hand_fwd_adj": (hf + hb) / (fwd_ms + bwd_ms)}
+
     # plain one-launch-per-step comparator on the same GPU and inputs
     if not args.no_plain:
         pdesc = prog.make_desc(x0, k0, om, pt, mode=rgb.PLAIN, use_hipgraph=False, **kw, **outs)

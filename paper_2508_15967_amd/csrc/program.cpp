@@ -179,22 +179,31 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         I.adj_step_flops_issued = I.rk4_step_flops_issued + 3 * fl_rhs.issued + 4 * fl_vjp.issued + rec;
     }
 
-    // ---- full source and hipRTC compile
-    p->full_src = std::string("// generated by raygraph\n") + RG_SRC_KERNELS;
-    p->hash = fnv1a(p->config_src.data(), p->config_src.size());
-    p->hash = fnv1a(p->functions_src.data(), p->functions_src.size(), p->hash);
-    p->hash = fnv1a(p->full_src.data(), p->full_src.size(), p->hash);
+    // ---- full source: one self-contained translation unit (headers spliced
+    // in), compilable by hipRTC or by hipcc
+    auto splice = [&](std::string text) {
+        const std::pair<const char *, std::string> inc[] = {
+            {"#include \"rg_kargs.h\"", RG_SRC_KARGS},
+            {"#include \"rg_config.h\"", p->config_src},
+            {"#include \"rg_prelude.h\"", RG_SRC_PRELUDE},
+            {"#include \"rg_functions.h\"", p->functions_src}};
+        for (const auto &kv : inc) {
+            size_t pos = text.find(kv.first);
+            if (pos != std::string::npos) text.replace(pos, std::strlen(kv.first), kv.second);
+        }
+        return text;
+    };
+    p->full_src = std::string("// generated by raygraph\n#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n") +
+                  splice(RG_SRC_KERNELS);
+    p->hash = fnv1a(p->full_src.data(), p->full_src.size());
     I.source_hash = p->hash;
 
     const char *arch = opts.arch ? opts.arch : "gfx950";
     std::string arch_opt = std::string("--offload-arch=") + arch;
     int olvl = opts.opt_level > 0 ? opts.opt_level : 3;
     std::string o_opt = "-O" + std::to_string(olvl);
-    const char *hnames[] = {"rg_kargs.h", "rg_config.h", "rg_prelude.h", "rg_functions.h"};
-    std::string fsrc = p->functions_src;
-    const char *hsrcs[] = {RG_SRC_KARGS, p->config_src.c_str(), RG_SRC_PRELUDE, fsrc.c_str()};
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, p->full_src.c_str(), "raygraph_kernels.hip", 4, hsrcs, hnames) !=
+    if (hiprtcCreateProgram(&prog, p->full_src.c_str(), "raygraph_kernels.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         return fail(RG_ECOMPILE, "hiprtcCreateProgram failed");
     // no FP contraction beyond the fma written in the source; no packed FP32
