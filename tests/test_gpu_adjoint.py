@@ -143,13 +143,16 @@ def test_aniso_adjoint_scales_vs_fd():
     s = pt[0]
     loss = lambda: _per_ray_loss(prog, x0, k0, om, pt, w)
     checked = 0
+    # a blob that no ray comes near has a gradient at the rounding level of
+    # the largest one (or exactly 0 by FD): absolute floor 1e-12 of the max
+    floor = 1e-12 * np.abs(g["gp"][0]).max()
     for p in range(16):
         def sets(v, p=p):
             s[p] = v
         fd, noise = _fd(loss, sets, s[p].item())
         ad = g["gp"][0][p]
         print(f"scale {p}: adjoint {ad:.12e} fd {fd:.12e} noise {noise:.1e}")
-        assert abs(ad - fd) <= FD_TOL * abs(fd) + 3 * noise, (p, ad, fd, noise)
+        assert abs(ad - fd) <= FD_TOL * abs(fd) + 3 * noise + floor, (p, ad, fd, noise)
         checked += noise < 1e-7 * abs(fd)
     assert checked >= 8
 
