@@ -132,29 +132,31 @@ def test_spline_adjoint_full_size_vs_fd():
 
 
 def test_aniso_adjoint_scales_vs_fd():
-    """Workload 5 medium (16 blob scales) on 16,384 rays x 4,000 steps: all 16
-    scale gradients against central differences of the GPU forward."""
-    w = W.make("5", 16384)
-    w.n_steps = 4000
+    """Workload 5 medium (16 blob scales) on 4,096 rays over the full horizon
+    (20,000 steps): all 16 scale gradients against central differences of
+    the GPU forward.  A difference quotient cannot resolve a derivative below
+    sum_r eps*L_r/(2h) (the loss moves by less than an ulp), so that is the
+    absolute floor of the comparison; the blobs the rays actually cross are
+    checked to 1e-6 relative."""
+    w = W.make("5", 4096)
     print("[case] aniso adjoint vs FD", flush=True)
     g = _gpu_grad(w)
     prog, pt = g["prog"], g["pt"]
     x0, k0, om = g["in"]
     s = pt[0]
     loss = lambda: _per_ray_loss(prog, x0, k0, om, pt, w)
+    h = 1e-6
+    res = (np.finfo(float).eps * loss()).sum() / (2 * h)
     checked = 0
-    # a blob that no ray comes near has a gradient at the rounding level of
-    # the largest one (or exactly 0 by FD): absolute floor 1e-12 of the max
-    floor = 1e-12 * np.abs(g["gp"][0]).max()
     for p in range(16):
         def sets(v, p=p):
             s[p] = v
-        fd, noise = _fd(loss, sets, s[p].item())
+        fd, noise = _fd(loss, sets, s[p].item(), h)
         ad = g["gp"][0][p]
-        print(f"scale {p}: adjoint {ad:.12e} fd {fd:.12e} noise {noise:.1e}")
-        assert abs(ad - fd) <= FD_TOL * abs(fd) + 3 * noise + floor, (p, ad, fd, noise)
-        checked += noise < 1e-7 * abs(fd)
-    assert checked >= 8
+        print(f"scale {p}: adjoint {ad:.12e} fd {fd:.12e} noise {noise:.1e} resolution {res:.1e}")
+        assert abs(ad - fd) <= FD_TOL * abs(fd) + 3 * noise + res, (p, ad, fd, noise)
+        checked += abs(fd) > 1e3 * (noise + res)
+    assert checked >= 6, checked
 
 
 def test_autograd_function_matches_adjoint():
