@@ -87,7 +87,7 @@ def test_status_paths_match_oracle(oracle):
     assert g["status"][0] == rgb.RAY_NONFINITE and g["status"][3] == rgb.RAY_NONFINITE
     assert g["status"][1] == rgb.RAY_EXITED_BOX and g["steps"][1] == 1
     assert g["status"][2] == rgb.RAY_BUDGET and g["steps"][2] == 1
-    fin = np.isfinite(o["x"]).all(0)
+    fin = np.isfinite(o["x"]).all(0) & np.isfinite(o["k"]).all(0)
     ex, ek = U.ray_errors(g, o, w.omega, w.dim)
     assert ex[fin].max() < U.TOL and ek[fin].max() < U.TOL
     # RK4 with a non-finite start freezes at the start with NONFINITE
