@@ -10,13 +10,19 @@
 namespace rg {
 
 const IssuedWeights &issued_weights() {
-    // FP64 flops in the gfx950 instruction sequence of each operation, read
-    // from the AMD assembly of single-operation kernels built with hipRTC for
-    // gfx950 (v_fma_f64 = 2; v_add_f64, v_mul_f64, v_rcp_f64, v_sqrt_f64,
-    // v_div_fmas_f64 ... = 1 or 2 as their arithmetic; compares, class tests,
-    // ldexp/frexp, selects and integer ops = 0).
-    static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 29.0, /*log*/ 40.0, /*sqrt*/ 12.0,
-                                 /*sincos*/ 60.0};
+    // FP64 flops in the gfx950 instruction sequence of each operation,
+    // counted in the AMD assembly of single-operation kernels compiled here
+    // (hipcc --offload-arch=gfx950 -O3 -ffp-contract=off): v_fma_f64 and
+    // v_div_fmas_f64 = 2; v_add_f64, v_mul_f64, v_rcp_f64, v_rsq_f64 = 1;
+    // compares, class tests, ldexp/frexp, rounding, conversions and selects = 0.
+    //   exp: 13 fma + 1 mul              = 27
+    //   div: 5 fma + div_fmas + mul + rcp = 14
+    //   sqrt: 7 fma + 2 mul + rsq         = 17
+    //   log: 14 fma + 43 add + 7 mul + rcp = 79
+    //   sin/cos: 24 fma + 56 add + 11 mul = 115
+    //   pow: 42 fma + 70 add + 11 mul + rcp = 166
+    static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 27.0, /*log*/ 79.0, /*sqrt*/ 17.0,
+                                 /*sincos*/ 115.0, /*pow*/ 166.0};
     return w;
 }
 
