@@ -21,8 +21,9 @@ const IssuedWeights &issued_weights() {
     //   log: 14 fma + 43 add + 7 mul + rcp = 79
     //   sin/cos: 24 fma + 56 add + 11 mul = 115
     //   pow: 42 fma + 70 add + 11 mul + rcp = 166
+    //   rg_rcp (reciprocal, rcp + two Newton steps): rcp + 4 fma = 9
     static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 27.0, /*log*/ 79.0, /*sqrt*/ 17.0,
-                                 /*sincos*/ 115.0, /*pow*/ 166.0};
+                                 /*sincos*/ 115.0, /*pow*/ 166.0, /*rcp*/ 9.0};
     return w;
 }
 
@@ -220,7 +221,15 @@ struct Emitter {
             break;
         }
         case MUL: e = A + " * " + B; count(MUL); break;
-        case DIV: e = A + " / " + B; count(DIV); break;
+        case DIV:
+            if (g.is_const(nd.a, 1.0)) {
+                e = "rg_rcp(" + B + ")";
+                fl.alg += 1; fl.issued += issued_weights().rcp; fl.ops++;
+            } else {
+                e = A + " / " + B;
+                count(DIV);
+            }
+            break;
         case NEG: e = "-" + A; break;
         case EXP: e = "exp(" + A + ")"; count(EXP); break;
         case LOG: e = "log(" + A + ")"; count(LOG); break;

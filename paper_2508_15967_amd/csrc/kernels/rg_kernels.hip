@@ -99,18 +99,27 @@ __device__ __forceinline__ bool rg_outside(const rg_kargs &a, const double *y) {
 
 // One classic RK4 step (weights 1/6, 1/3, 1/3, 1/6), fused: the stage
 // vectors live in registers and the update accumulates as the stages come.
+// Components whose right-hand side is identically zero (RG_RHS_ZERO, known
+// when the graph is compiled) keep their value through every stage: the
+// stage arithmetic would add exact zeros to them.
+#define RG_ZERO(i) ((RG_RHS_ZERO >> (i)) & 1u)
+
 __device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t, double dt,
                                             const rg_P &P, double *yn) {
     const double h2 = 0.5 * dt, dt6 = dt / 6.0;
     double K[RG_NY], acc[RG_NY], Y[RG_NY];
     rg_rhs(y, om, t, P, K);
-    for (int i = 0; i < RG_NY; i++) { acc[i] = K[i]; Y[i] = fma(h2, K[i], y[i]); }
+    for (int i = 0; i < RG_NY; i++) { acc[i] = K[i]; Y[i] = RG_ZERO(i) ? y[i] : fma(h2, K[i], y[i]); }
     rg_rhs(Y, om, t + h2, P, K);
-    for (int i = 0; i < RG_NY; i++) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(h2, K[i], y[i]); }
+    for (int i = 0; i < RG_NY; i++) {
+        if (!RG_ZERO(i)) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(h2, K[i], y[i]); }
+    }
     rg_rhs(Y, om, t + h2, P, K);
-    for (int i = 0; i < RG_NY; i++) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
+    for (int i = 0; i < RG_NY; i++) {
+        if (!RG_ZERO(i)) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
+    }
     rg_rhs(Y, om, t + dt, P, K);
-    for (int i = 0; i < RG_NY; i++) { acc[i] = acc[i] + K[i]; yn[i] = fma(dt6, acc[i], y[i]); }
+    for (int i = 0; i < RG_NY; i++) yn[i] = RG_ZERO(i) ? y[i] : fma(dt6, acc[i] + K[i], y[i]);
 }
 
 // ------------------------------------------------------- persistent RK4 --

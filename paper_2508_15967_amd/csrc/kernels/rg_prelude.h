@@ -14,6 +14,22 @@ struct rg_P {
     const double *p[RG_MAX_PARAMS];
 };
 
+// 1/d: the hardware reciprocal estimate refined by two Newton steps
+// r <- r + r (1 - d r), within one ulp of 1/d for normal finite d (the
+// correctly rounded division takes about twice the instructions).  d = 0,
+// +-inf and subnormal d give a non-finite result instead of +-inf / 0.
+RG_FN double rg_rcp(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-d, r, 1.0);
+    return fma(e, r, r);
+#else
+    return 1.0 / d;
+#endif
+}
+
 // Cell of a uniform cubic B-spline with n coefficients: s = (x - lo)/h + 1,
 // m = clamp(floor(s), 1, n - 3), u = s - m (u leaves [0,1] outside the
 // domain, extending the edge cell's cubic).  4 flops.

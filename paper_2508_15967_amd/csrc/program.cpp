@@ -59,11 +59,21 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     const uint32_t Dw = g.df(D, om);
     if (g.is_const(Dw, 0.0)) return fail(RG_EINVAL, "dD/domega is identically zero");
     const uint32_t inv = g.div(g.constant(1.0), Dw);
+    // a partial of the form c*u is multiplied as (c*inv)*u, so the scaled
+    // reciprocal c*inv is one shared node (e.g. dD/dk_i = 2 k_i for all i)
+    auto times_inv = [&](uint32_t a) {
+        const Node &na = g.node(a);
+        if (na.op == MUL && g.is_const(na.a)) return g.mul(g.mul(na.a, inv), na.b);
+        return g.mul(a, inv);
+    };
     std::vector<uint32_t> f(ny);
     for (uint32_t i = 0; i < d; i++) {
-        f[i] = g.neg(g.mul(g.df(D, yv[d + i]), inv));
-        f[d + i] = g.mul(g.df(D, yv[i]), inv);
+        f[i] = g.neg(times_inv(g.df(D, yv[d + i])));
+        f[d + i] = times_inv(g.df(D, yv[i]));
     }
+    unsigned zero_mask = 0;  // components whose right-hand side is identically 0
+    for (uint32_t i = 0; i < ny; i++)
+        if (g.is_const(f[i], 0.0)) zero_mask |= 1u << i;
 
     // ---- spline tables used by the program
     std::vector<uint32_t> roots(f.begin(), f.end());
@@ -142,7 +152,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     cs << "#pragma once\n#define RG_DIM " << d << "\n#define RG_NY " << ny << "\n#define RG_NPARAM "
        << p->n_params << "\n#define RG_NGRAD " << p->grad_param.size() << "\n#define RG_NSPLTAB "
        << p->spl_param.size() << "\n#define RG_SPL_TOTAL " << (p->spl_total ? p->spl_total : 1)
-       << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n";
+       << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_RHS_ZERO " << zero_mask
+       << "u\n";
     cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)
        << int_array("rg_spl_len", p->spl_len) << int_array("rg_spl_ny", p->spl_ny)
        << int_array("rg_grad_param", p->grad_param) << int_array("rg_grad_elem", p->grad_elem);

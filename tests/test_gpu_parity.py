@@ -125,3 +125,21 @@ def test_dopri_bumps_subset(oracle):
     ex, ek = U.ray_errors(g, o, w.omega, w.dim)
     ok = same & ~bad
     assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+
+
+def test_reciprocal_within_one_ulp():
+    """The emitted reciprocal of dD/domega (hardware estimate + two Newton
+    steps) is within 1 ulp of the correctly rounded 1/d: homogeneous medium,
+    dx/dt = k/(omega N0) = 2k * (1/(2 omega N0)), over omega spanning decades."""
+    torch = U.torch_mod()
+    w = W.homog(n_rays=4096, dim=3, N0=1.0)
+    _, _, prog, _ = U.program(w)
+    rng = np.random.default_rng(11)
+    om = 10.0 ** rng.uniform(-3, 3, 4096)
+    y = np.concatenate([rng.uniform(-1, 1, (3, 4096)), np.ones((3, 4096))])
+    f, _ = prog.eval(U.dev(y), U.dev(om))
+    torch.cuda.synchronize()
+    got = f.cpu().numpy()[0]
+    ref = 2.0 * (1.0 / (2.0 * om))      # k = 1: f = 2 * rcp(2 omega N0) exactly rounded
+    ulps = np.abs(got - ref) / np.spacing(np.abs(ref))
+    assert ulps.max() <= 1.0, ulps.max()
