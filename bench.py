@@ -82,6 +82,8 @@ def main():
             "t_out": torch.empty(n, dtype=torch.float64, device=dev),
             "status_out": torch.empty(n, dtype=torch.int32, device=dev),
             "steps_out": torch.empty(n, dtype=torch.int32, device=dev)}
+    if w.integrator == W.DOPRI54:
+        outs["attempts_out"] = torch.empty(n, dtype=torch.int32, device=dev)
     if w.store_every > 0:
         ns = w.n_steps // w.store_every + 1
         outs["traj"] = torch.empty((ns, ny, n), dtype=torch.float64, device=dev)
@@ -162,10 +164,10 @@ def main():
         flops_alg = info["rk4_step_flops_alg"] * ray_steps
         flops_iss = info["rk4_step_flops_issued"] * ray_steps
     else:
-        # attempts are not returned per ray; accepted steps x attempt cost is
-        # a lower bound of the work done
-        flops_alg = info["dopri_attempt_flops_alg"] * ray_steps
-        flops_iss = info["dopri_attempt_flops_issued"] * ray_steps
+        # every attempt (accepted or rejected) costs one attempt's flops
+        attempts = int(outs["attempts_out"].cpu().numpy().astype(np.int64).sum())
+        flops_alg = info["dopri_attempt_flops_alg"] * attempts
+        flops_iss = info["dopri_attempt_flops_issued"] * attempts
     kernel_ms = fwd_ms
     if adjoint:
         flops_alg_adj = info["adj_step_flops_alg"] * ray_steps

@@ -232,6 +232,7 @@ typedef struct {
     int32_t rays_per_lane;      /* 1 | 2, 0 = tuned */
     int32_t compact_interval;   /* DOPRI54: refill dead lanes every this many attempts,
                                    0 = tuned, -1 = only when a whole wave is dead */
+    int32_t *attempts_out;      /* DOPRI54: [n] step attempts incl. rejected ones, nullable */
 } rg_trace_desc;
 
 /* Trace n_rays rays.  RK4 runs exactly n_steps steps per ray (fewer if it

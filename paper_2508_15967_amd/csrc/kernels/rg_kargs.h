@@ -12,7 +12,7 @@ struct rg_kargs {
     const int *budget;
     // outputs
     double *x_out, *k_out, *t_out;
-    int *status_out, *steps_out;
+    int *status_out, *steps_out, *attempts_out;
     double *traj, *traj_D, *ckpt;
     // adjoint
     const double *lam_x, *lam_k;

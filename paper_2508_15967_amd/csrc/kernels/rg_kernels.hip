@@ -415,6 +415,7 @@ __device__ __forceinline__ void rg_dp_store(const rg_kargs &a, long long id, rg_
     if (a.t_out) a.t_out[id] = r.t;
     if (a.status_out) a.status_out[id] = r.st;
     if (a.steps_out) a.steps_out[id] = r.acc;
+    if (a.attempts_out) a.attempts_out[id] = r.att;
 }
 
 // Persistent adaptive kernel with wave-level compaction: every `compact`

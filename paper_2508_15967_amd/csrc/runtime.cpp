@@ -279,6 +279,8 @@ static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
         if (!(d.h0 > 0.0) || !(d.rtol >= 0.0) || !(d.atol >= 0.0) || !(d.rtol + d.atol > 0.0))
             return fail(RG_EINVAL, "DOPRI54 needs h0 > 0 and rtol + atol > 0");
         if (d.budget) RGCHK(check_dev(d.budget, 4 * n, "budget"));
+        if (d.attempts_out) RGCHK(check_dev(d.attempts_out, 4 * n, "attempts_out"));
+        a.attempts_out = d.attempts_out;
         a.budget = d.budget;
         a.max_steps = d.max_steps;
         a.h0 = d.h0; a.rtol = d.rtol; a.atol = d.atol; a.hmin = d.hmin; a.t_end = d.t_end;

@@ -107,7 +107,8 @@ class TraceDesc(C.Structure):
                 ("status_out", C.c_void_p), ("steps_out", C.c_void_p),
                 ("checkpoint_every", C.c_int32), ("checkpoints", C.c_void_p),
                 ("mode", C.c_int32), ("use_hipgraph", C.c_int32), ("block", C.c_int32),
-                ("rays_per_lane", C.c_int32), ("compact_interval", C.c_int32)]
+                ("rays_per_lane", C.c_int32), ("compact_interval", C.c_int32),
+                ("attempts_out", C.c_void_p)]
 
 
 class AdjointDesc(C.Structure):
@@ -372,14 +373,14 @@ class Program:
                   t0=None, store_every=0, traj=None, traj_D=None, x_out=None, k_out=None,
                   t_out=None, status_out=None, steps_out=None, checkpoint_every=0,
                   checkpoints=None, mode=PERSISTENT, use_hipgraph=False, block=0,
-                  rays_per_lane=0, compact_interval=0):
+                  rays_per_lane=0, compact_interval=0, attempts_out=None):
         import torch
         f64, i32 = torch.float64, torch.int32
         for t, nm, dt_ in ((x0, "x0", f64), (k0, "k0", f64), (omega, "omega", f64), (t0, "t0", f64),
                            (budget, "budget", i32), (traj, "traj", f64), (traj_D, "traj_D", f64),
                            (x_out, "x_out", f64), (k_out, "k_out", f64), (t_out, "t_out", f64),
                            (status_out, "status_out", i32), (steps_out, "steps_out", i32),
-                           (checkpoints, "checkpoints", f64)):
+                           (checkpoints, "checkpoints", f64), (attempts_out, "attempts_out", i32)):
             _check_tensor(t, nm, dt_)
         if len(params) != len(self.param_lens):
             raise ValueError(f"expected {len(self.param_lens)} parameter arrays, got {len(params)}")
@@ -406,6 +407,7 @@ class Program:
         d.checkpoint_every, d.checkpoints = int(checkpoint_every), _dptr(checkpoints)
         d.mode, d.use_hipgraph = int(mode), int(bool(use_hipgraph))
         d.block, d.rays_per_lane, d.compact_interval = int(block), int(rays_per_lane), int(compact_interval)
+        d.attempts_out = _dptr(attempts_out)
         return d
 
     def trace_desc(self, d: TraceDesc, stream=None):
@@ -441,6 +443,8 @@ class Program:
                "t": torch.empty(n, dtype=torch.float64, device=dev),
                "status": torch.empty(n, dtype=torch.int32, device=dev),
                "steps": torch.empty(n, dtype=torch.int32, device=dev)}
+        if kw.get("integrator", RK4) == DOPRI54:
+            out["attempts"] = torch.empty(n, dtype=torch.int32, device=dev)
         se = int(kw.pop("store_every", 0))
         if (store or store_D) and se > 0:
             ns = int(kw.get("n_steps", 0)) // se + 1
@@ -457,7 +461,7 @@ class Program:
                               traj_D=out.get("traj_D"), x_out=out["x"], k_out=out["k"],
                               t_out=out["t"], status_out=out["status"], steps_out=out["steps"],
                               checkpoint_every=checkpoint_every, checkpoints=out.get("checkpoints"),
-                              **kw)
+                              attempts_out=out.get("attempts"), **kw)
         self.trace_desc(desc, stream)
         out["_desc"] = desc
         return out
