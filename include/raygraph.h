@@ -267,6 +267,30 @@ rg_status rg_eval_rays(rg_program *p, uint32_t n, const double *y, const double 
                        const double *t, const double *const *params, double *f_out,
                        double *D_out, void *hip_stream);
 
+/* Launch conditions by Newton's method (paper, end of the "Impact" section:
+ * omega, x and all but one wavevector component are fixed and the remaining
+ * component is found by Newton iteration until |D| < 1e-15; the initial
+ * guess selects the branch of the multi-valued dispersion relation).  Each
+ * ray iterates k_c <- k_c - D / (dD/dk_c) in its own lane until
+ * |D| <= tol or max_iter; the largest final |D| over all rays is reduced
+ * into *max_abs_D (the convergence test of the paper's Newton workflow). */
+typedef struct {
+    uint32_t struct_size;       /* sizeof(rg_solve_desc) */
+    uint32_t n_rays;
+    const double *x;            /* [dim][n] */
+    double *k;                  /* [dim][n]: initial guess in, solution out */
+    const double *omega;        /* [n] */
+    const double *t;            /* [n], NULL = 0 */
+    const double *const *params;/* host array of n_params device pointers */
+    int32_t component;          /* index of the k component solved for */
+    int32_t max_iter;           /* > 0 */
+    double tol;                 /* |D| tolerance, e.g. 1e-15 */
+    double *D_out;              /* [n] final D, nullable */
+    int32_t *iters_out;         /* [n] iterations used, -1 if not converged, nullable */
+    double *max_abs_D;          /* device scalar: max |D| after the solve, nullable */
+} rg_solve_desc;
+rg_status rg_solve_k(rg_program *p, const rg_solve_desc *d, void *hip_stream);
+
 typedef struct {
     uint32_t struct_size;
     int32_t block, rays_per_lane, compact_interval; /* last configuration used */

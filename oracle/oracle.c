@@ -794,3 +794,55 @@ void om_dopri_tableau(double *c, double *a, double *b5, double *b4)
         for (int j = 0; j < 6; j++) a[i * 6 + j] = DP_A[i][j];
     }
 }
+
+/* dD/dk by hand: isotropic media and the O-mode profile 2k; anisotropic
+ * medium 2 A k. */
+static void om_Dk(const om_medium *m, const double *y, double *Dk)
+{
+    int d = m->dim;
+    const double *x = y, *k = y + d;
+    if (m->kind != ANISO3D) {
+        for (int i = 0; i < d; i++) Dk[i] = 2.0 * k[i];
+        return;
+    }
+    double Ak[3] = {k[0], k[1], k[2]};
+    for (int b = 0; b < m->nb; b++) {
+        const double *c = m->centers + 3 * b;
+        double w2 = m->widths[b] * m->widths[b], r2 = 0.0;
+        for (int i = 0; i < 3; i++) r2 += (x[i] - c[i]) * (x[i] - c[i]);
+        double gb = exp(-r2 / w2), M[9];
+        sym3(m->mats + 6 * b, M);
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) Ak[i] += m->scales[b] * gb * M[i * 3 + j] * k[j];
+    }
+    for (int i = 0; i < 3; i++) Dk[i] = 2.0 * Ak[i];
+}
+
+/* Launch conditions ("Impact" section): Newton's method on k_c with x, omega
+ * and the other components fixed, k_c <- k_c - D / (dD/dk_c), until
+ * |D| <= tol or max_iter iterations.  k is SoA [dim][n], updated in place;
+ * iters_out gets the iteration count (-1 if not converged). */
+int om_newton_k(const om_medium *m, int64_t n, const double *x, double *k, const double *omega,
+                int c, double tol, int max_iter, int32_t *iters_out, double *D_out)
+{
+    int d = m->dim;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; r++) {
+        double y[MAXY], Dk[MAXD];
+        for (int i = 0; i < d; i++) { y[i] = x[i * n + r]; y[d + i] = k[i * n + r]; }
+        int it = 0, done = 0;
+        double D = om_D1(m, y, omega[r]);
+        for (;;) {
+            if (fabs(D) <= tol) { done = 1; break; }
+            if (it >= max_iter || !isfinite(D)) break;
+            om_Dk(m, y, Dk);
+            y[d + c] = y[d + c] - D / Dk[c];
+            it++;
+            D = om_D1(m, y, omega[r]);
+        }
+        for (int i = 0; i < d; i++) k[i * n + r] = y[d + i];
+        if (iters_out) iters_out[r] = done ? it : -1;
+        if (D_out) D_out[r] = D;
+    }
+    return 0;
+}

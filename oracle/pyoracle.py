@@ -218,3 +218,17 @@ def dopri_tableau():
     c, a, b5, b4 = np.zeros(7), np.zeros((7, 6)), np.zeros(7), np.zeros(7)
     lib().om_dopri_tableau(_ptr(c), _ptr(a), _ptr(b5), _ptr(b4))
     return c, a, b5, b4
+
+
+def newton_k(medium, x, k, omega, component=0, tol=1e-15, max_iter=50):
+    """Newton solve of D = 0 for k[component]; returns (k, iters, D)."""
+    med = Medium(medium)
+    x = _f64(x)
+    k = np.array(k, dtype=np.float64, copy=True, order="C")
+    n = x.shape[1]
+    om = _f64(np.broadcast_to(omega, (n,)))
+    it = np.zeros(n, np.int32)
+    D = np.zeros(n)
+    lib().om_newton_k(C.byref(med.s), C.c_int64(n), _ptr(x), _ptr(k), _ptr(om), C.c_int(component),
+                      C.c_double(tol), C.c_int(max_iter), _ptr(it), _ptr(D))
+    return k, it, D

@@ -271,6 +271,13 @@ rg_status rg_trace_rays_adjoint(rg_program *p, const rg_adjoint_desc *d, void *s
     GUARD_END
 }
 
+rg_status rg_solve_k(rg_program *p, const rg_solve_desc *d, void *stream) {
+    if (!p || !d) return fail(RG_EINVAL, "NULL argument");
+    GUARD_BEGIN
+    return rg::solve_k(p, *d, (hipStream_t)stream);
+    GUARD_END
+}
+
 rg_status rg_eval_rays(rg_program *p, uint32_t n, const double *y, const double *omega,
                        const double *t, const double *const *params, double *f_out,
                        double *D_out, void *stream) {

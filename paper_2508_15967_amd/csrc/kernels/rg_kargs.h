@@ -35,6 +35,11 @@ struct rg_kargs {
     int step, snap, ckpt_idx, count_alive;
     long long scratch_lanes;
     int n_part, part_stride;
+    // Newton solve
+    double *k_io, *D_out, *max_abs_D;
+    int *iters_out;
+    int component, max_iter;
+    double tol;
     long long fill_n;
     double fill_v;
     double *fill_p;

@@ -530,6 +530,49 @@ extern "C" __global__ void __launch_bounds__(512) rg_dopri_plain_step(rg_kargs a
     else if (a.count_alive) atomicAdd(a.counter, 1);
 }
 
+// --------------------------------------------------------- Newton solve --
+// k_c <- k_c - D/(dD/dk_c) per ray until |D| <= tol; the largest final |D|
+// is reduced per wave and folded into a device scalar with one atomic max on
+// its bit pattern (non-negative doubles order like their bits).
+extern "C" __global__ void __launch_bounds__(512) rg_newton_k(rg_kargs a) {
+    rg_stage_tables(a);
+    const long long n = a.n;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double absD = 0.0;
+    if (r < a.n_run) {
+        const rg_P P = rg_params(a);
+        double y[RG_NY], g[RG_DIM + 1];
+        for (int i = 0; i < RG_DIM; i++) {
+            y[i] = a.x0[i * n + r];
+            y[RG_DIM + i] = a.k_io[i * n + r];
+        }
+        const double om = a.omega[r], t = a.t0 ? a.t0[r] : 0.0;
+        const int c = a.component;
+        int it = 0, done = 0;
+        for (;;) {
+            rg_Dk(y, om, t, P, g);
+            if (fabs(g[0]) <= a.tol) { done = 1; break; }
+            if (it >= a.max_iter || !__builtin_isfinite(g[0])) break;
+            double dk = 0.0;
+            for (int i = 0; i < RG_DIM; i++) dk = (i == c) ? g[1 + i] : dk;
+            double kc = 0.0;
+            for (int i = 0; i < RG_DIM; i++) kc = (i == c) ? y[RG_DIM + i] : kc;
+            kc = kc - g[0] / dk;
+            for (int i = 0; i < RG_DIM; i++) y[RG_DIM + i] = (i == c) ? kc : y[RG_DIM + i];
+            it++;
+        }
+        for (int i = 0; i < RG_DIM; i++) a.k_io[i * n + r] = y[RG_DIM + i];
+        if (a.D_out) a.D_out[r] = g[0];
+        if (a.iters_out) a.iters_out[r] = done ? it : -1;
+        absD = __builtin_isfinite(g[0]) ? fabs(g[0]) : __builtin_inf();
+    }
+    if (a.max_abs_D) {
+        for (int off = 32; off > 0; off >>= 1) absD = fmax(absD, __shfl_xor(absD, off));
+        if ((threadIdx.x & 63) == 0)
+            atomicMax((unsigned long long *)a.max_abs_D, (unsigned long long)__double_as_longlong(absD));
+    }
+}
+
 // ----------------------------------------------------------------- utils --
 extern "C" __global__ void __launch_bounds__(512) rg_fill_f64(rg_kargs a) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

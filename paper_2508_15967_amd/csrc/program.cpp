@@ -116,6 +116,18 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         spec.returns_value = true;
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
+    {
+        // D and dD/dk (Newton solve for launch conditions)
+        FunctionSpec spec;
+        spec.signature =
+            "RG_FN void rg_Dk(const double *__restrict__ y, const double om, const double t, "
+            "const rg_P &P, double *__restrict__ out) {\n  (void)om; (void)t; (void)P; (void)y;";
+        spec.outputs.push_back({D, "out[0]", false});
+        for (uint32_t i = 0; i < d; i++)
+            spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
+        Flops fl_dk;
+        fs << emit_function(g, spec, table_slot, &fl_dk);
+    }
     p->info.n_nodes_rhs = fl_rhs.ops;
 
     // ---- emit the VJP

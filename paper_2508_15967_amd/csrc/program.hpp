@@ -62,6 +62,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
 // Runtime (runtime.cpp).
 rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s);
 rg_status adjoint(rg_program *p, const rg_adjoint_desc &d, hipStream_t s);
+rg_status solve_k(rg_program *p, const rg_solve_desc &d, hipStream_t s);
 rg_status eval_points(rg_program *p, uint32_t n, const double *y, const double *omega,
                       const double *t, const double *const *params, double *f, double *D,
                       hipStream_t s);

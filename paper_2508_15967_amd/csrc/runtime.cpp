@@ -31,7 +31,7 @@ namespace rg {
 static const char *const KERNELS[] = {
     "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
     "rg_dopri_persistent", "rg_dopri_plain_init", "rg_dopri_plain_step", "rg_fill_f64",
-    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize"};
+    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k"};
 
 static void drop_graphs(rg_program *p) {
     for (GraphEntry &ge : p->graphs) {
@@ -589,6 +589,52 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     p->last.block = block;
     p->last.grid = (int)grid;
     return RG_OK;
+}
+
+rg_status solve_k(rg_program *p, const rg_solve_desc &d, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    if (d.struct_size < sizeof(rg_solve_desc)) return fail(RG_EINVAL, "rg_solve_desc.struct_size too small");
+    if (d.component < 0 || d.component >= (int)p->dim) return fail(RG_EINVAL, "component out of range");
+    if (d.max_iter <= 0 || d.max_iter > 1000) return fail(RG_EINVAL, "max_iter must be in 1..1000");
+    if (!(d.tol >= 0.0)) return fail(RG_EINVAL, "tol must be >= 0");
+    const size_t n = d.n_rays;
+    if (n == 0) return RG_OK;
+    const uint32_t dim = p->dim;
+    rg_kargs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = (long long)n;
+    a.n_run = (long long)n;
+    RGCHK(check_dev(d.x, 8 * dim * n, "x"));
+    RGCHK(check_dev(d.k, 8 * dim * n, "k"));
+    RGCHK(check_dev(d.omega, 8 * n, "omega"));
+    if (d.t) RGCHK(check_dev(d.t, 8 * n, "t"));
+    if (d.D_out) RGCHK(check_dev(d.D_out, 8 * n, "D_out"));
+    if (d.iters_out) RGCHK(check_dev(d.iters_out, 4 * n, "iters_out"));
+    if (d.max_abs_D) RGCHK(check_dev(d.max_abs_D, 8, "max_abs_D"));
+    if (p->n_params > 0 && !d.params) return fail(RG_EINVAL, "params is NULL but the graph has parameters");
+    for (uint32_t i = 0; i < p->n_params; i++) {
+        RGCHK(check_dev(d.params[i], 8 * (size_t)p->param_len[i], "params[i]"));
+        a.params[i] = d.params[i];
+    }
+    a.x0 = d.x;
+    a.k_io = d.k;
+    a.omega = d.omega;
+    a.t0 = d.t;
+    a.D_out = d.D_out;
+    a.iters_out = d.iters_out;
+    a.max_abs_D = d.max_abs_D;
+    a.component = d.component;
+    a.max_iter = d.max_iter;
+    a.tol = d.tol;
+    if (d.max_abs_D) {
+        rg_kargs f;
+        std::memset(&f, 0, sizeof f);
+        f.fill_p = d.max_abs_D;
+        f.fill_n = 1;
+        f.fill_v = 0.0;
+        RGCHK(launch_one(p, Launch{"rg_fill_f64", 1, 64, f}, s));
+    }
+    return launch_one(p, Launch{"rg_newton_k", cdiv(n, 256), 256, a}, s);
 }
 
 rg_status eval_points(rg_program *p, uint32_t n, const double *y, const double *omega,

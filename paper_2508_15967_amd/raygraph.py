@@ -62,6 +62,7 @@ SYMBOLS = [
     "rg_df", "rg_node_get", "rg_graph_size", "rg_eval", "rg_node_to_string", "rg_compile",
     "rg_destroy_program", "rg_program_info_get", "rg_program_source", "rg_program_functions",
     "rg_trace_rays", "rg_trace_rays_adjoint", "rg_eval_rays", "rg_last_launch", "rg_last_error",
+    "rg_solve_k",
 ]
 
 
@@ -115,6 +116,13 @@ class AdjointDesc(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("fwd", C.POINTER(TraceDesc)),
                 ("dL_dx_end", C.c_void_p), ("dL_dk_end", C.c_void_p), ("dL_dx0", C.c_void_p),
                 ("dL_dk0", C.c_void_p), ("dL_dparams", C.c_void_p)]
+
+
+class SolveDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_rays", C.c_uint32), ("x", C.c_void_p),
+                ("k", C.c_void_p), ("omega", C.c_void_p), ("t", C.c_void_p), ("params", C.c_void_p),
+                ("component", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("D_out", C.c_void_p), ("iters_out", C.c_void_p), ("max_abs_D", C.c_void_p)]
 
 
 class LaunchInfo(C.Structure):
@@ -465,6 +473,28 @@ class Program:
         self.trace_desc(desc, stream)
         out["_desc"] = desc
         return out
+
+    def solve_k(self, x, k, omega, params=(), component=0, tol=1e-15, max_iter=50, stream=None):
+        """Newton solve of D = 0 for k[component] in place (rg_solve_k).
+        Returns (iterations per ray, final D per ray, max |D| as a 1-element tensor)."""
+        import torch
+        for t, nm in ((x, "x"), (k, "k"), (omega, "omega")):
+            _check_tensor(t, nm, torch.float64)
+        n = int(x.shape[-1])
+        dev = x.device
+        it = torch.empty(n, dtype=torch.int32, device=dev)
+        D = torch.empty(n, dtype=torch.float64, device=dev)
+        mx = torch.empty(1, dtype=torch.float64, device=dev)
+        d = SolveDesc()
+        d.struct_size = C.sizeof(SolveDesc)
+        d.n_rays = n
+        d.x, d.k, d.omega = _dptr(x), _dptr(k), _dptr(omega)
+        pp = (C.c_void_p * max(1, len(params)))(*[_dptr(p) for p in params])
+        d.params = C.cast(pp, C.c_void_p).value if params else None
+        d.component, d.max_iter, d.tol = int(component), int(max_iter), float(tol)
+        d.D_out, d.iters_out, d.max_abs_D = _dptr(D), _dptr(it), _dptr(mx)
+        _chk(_lib.rg_solve_k(self.h, C.byref(d), C.c_void_p(_stream_handle(stream))), "rg_solve_k")
+        return it, D, mx
 
     def eval(self, y, omega, params=(), t=None, stream=None):
         """Right-hand side f [2d][n] and D [n] at points y [2d][n] on the GPU."""

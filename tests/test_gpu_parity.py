@@ -143,3 +143,29 @@ def test_reciprocal_within_one_ulp():
     ref = 2.0 * (1.0 / (2.0 * om))      # k = 1: f = 2 * rcp(2 omega N0) exactly rounded
     ulps = np.abs(got - ref) / np.spacing(np.abs(ref))
     assert ulps.max() <= 1.0, ulps.max()
+
+
+@pytest.mark.parametrize("cfg", ["1", "4", "5"])
+def test_newton_launch_conditions_match_oracle(oracle, cfg):
+    """GPU Newton solve of D = 0 for k_x (rg_solve_k) against the oracle's
+    Newton: same branch, roots within 1e-13, |D| <= 1e-15, and the reduced
+    max |D| equals the largest per-ray |D|."""
+    torch = U.torch_mod()
+    w = W.make(cfg, 4096)
+    rng = np.random.default_rng(31)
+    guess = w.k0.copy()
+    sign = np.where(rng.random(w.n) < 0.5, -1.0, 1.0)
+    guess[0] = sign * np.maximum(np.abs(guess[0]) * (1 + 0.2 * rng.uniform(-1, 1, w.n)), 0.05)
+    _, _, prog, params = U.program(w)
+    kt = U.dev(guess)
+    it, D, mx = prog.solve_k(U.dev(w.x0), kt, U.dev(w.omega), [U.dev(p) for p in params], 0, 1e-15, 50)
+    torch.cuda.synchronize()
+    ko, ito, Do = oracle.newton_k(w.medium, w.x0, guess, w.omega, 0, 1e-15, 50)
+    kg, itg, Dg = kt.cpu().numpy(), it.cpu().numpy(), D.cpu().numpy()
+    both = (itg >= 0) & (ito >= 0)
+    assert both.mean() > 0.95
+    assert np.all(np.sign(kg[0][both]) == sign[both])
+    assert np.abs(kg[0][both] - ko[0][both]).max() <= 1e-13 * np.abs(ko[0]).max()
+    assert np.abs(Dg[itg >= 0]).max() <= 1e-15
+    fin = np.isfinite(Dg)
+    assert mx.item() == np.abs(Dg[fin]).max() or not fin.all()

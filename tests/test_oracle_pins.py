@@ -421,3 +421,22 @@ def test_adjoint_homogeneous_closed_form(oracle):
     N0 = w.medium.p[0]
     assert np.abs(lam0[: w.dim] - 2 * (r["x"] - tgt)).max() < 1e-12
     assert np.abs(lam0[w.dim:] - 2 * (r["x"] - tgt) * T / (w.omega * N0)).max() < 1e-11
+
+
+def test_newton_launch_conditions_closed_form(oracle):
+    """Newton on k_x with x, omega, k_y (, k_z) fixed converges to |D| <= 1e-15
+    and to the closed-form root +-sqrt(w^2 N - k_perp^2) of an isotropic
+    medium; the sign of the initial guess picks the branch."""
+    rng = np.random.default_rng(21)
+    for cfg in ("1", "2", "4"):
+        w = W.make(cfg, 256)
+        guess = w.k0.copy()  # on the shell: a real root exists for k_x
+        sign = np.where(rng.random(w.n) < 0.5, -1.0, 1.0)
+        guess[0] = sign * np.maximum(np.abs(guess[0]) * (1 + 0.2 * rng.uniform(-1, 1, w.n)), 0.05)
+        k, it, D = oracle.newton_k(w.medium, w.x0, guess, w.omega, 0, 1e-15, 50)
+        conv = it >= 0
+        assert conv.mean() > 0.95
+        N = np.real(DD.N_of(w.medium, w.x0))
+        exact = sign * np.sqrt(w.omega ** 2 * N - (guess[1:] ** 2).sum(0))
+        assert np.abs(k[0][conv] - exact[conv]).max() < 1e-14 * np.abs(exact).max()
+        assert np.abs(D[conv]).max() <= 1e-15
