@@ -24,6 +24,7 @@
  * Built with -O2 -fno-fast-math -ffp-contract=off: no contraction, no
  * reassociation.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -33,7 +34,7 @@
 #endif
 
 enum { HOMOG = 0, OLINEAR = 1, LINEARN = 2, LENS2D = 3, STRAT3D = 4, BUMPS3D = 5,
-       SPLINE2D = 6, ANISO3D = 7 };
+       SPLINE2D = 6, ANISO3D = 7, COLDPLASMA = 8 };
 enum { RAY_OK = 0, RAY_EXITED_BOX = 1, RAY_BUDGET = 2, RAY_NONFINITE = 3,
        RAY_STEP_UNDERFLOW = 4 };
 
@@ -226,6 +227,57 @@ static void sym3(const double *m6, double M[9])
 }
 
 /* ------------------------------------------------------------------------ */
+/* cold plasma ("Cold Plasma Dispersion Relation", eqs. 5-10)                */
+/* B along z; electron density w_pe^2(x) = p0 (p1 x + 1) (eq. 4 profile);    */
+/* electron cyclotron frequency p2 (signed); ions of mass ratio p3 (0: none). */
+/* Units omega, c = 1: n = k / omega (eq. 6).                                 */
+
+static double complex cp_D(const om_medium *m, const double complex *x, const double complex *k,
+                           double complex w)
+{
+    /* dielectric tensor elements, eqs. 8-10 (X = w_p^2/w^2, Y = Omega/w) */
+    double complex X = m->p[0] * (m->p[1] * x[0] + 1.0) / (w * w);
+    double complex Y = m->p[2] / w;
+    double complex S = 1.0 - X / (1.0 - Y * Y);        /* eps_11 */
+    double complex G = Y * X / (1.0 - Y * Y);          /* eps_12 = -i G */
+    double complex P = 1.0 - X;                        /* eps_33 */
+    if (m->p[3] > 0.0) {
+        double complex Xi = X / m->p[3], Yi = -Y / m->p[3];
+        S = S - Xi / (1.0 - Yi * Yi);
+        G = G + Yi * Xi / (1.0 - Yi * Yi);
+        P = P - Xi;
+    }
+    /* D = Det(eps + n n - n^2 I), eq. 5; the off-diagonal entries are
+       eps_12 + n_x n_y = n_x n_y - i G and its conjugate, the rest real, so
+       the determinant of the Hermitian matrix is the real expression
+       M11 M22 M33 - M11 M23^2 - M22 M13^2 - (a^2 + G^2) M33 + 2 a M13 M23. */
+    double complex nx = k[0] / w, ny = k[1] / w, nz = k[2] / w;
+    double complex n2 = nx * nx + ny * ny + nz * nz;
+    double complex M11 = S + nx * nx - n2, M22 = S + ny * ny - n2, M33 = P + nz * nz - n2;
+    double complex a = nx * ny, M13 = nx * nz, M23 = ny * nz;
+    return M11 * M22 * M33 - M11 * M23 * M23 - M22 * M13 * M13 - (a * a + G * G) * M33
+           + 2.0 * a * M13 * M23;
+}
+
+/* Partial derivatives of the cold-plasma D by complex-step differentiation
+ * (Squire & Trapp 1998): dD/dv = Im D(v + i h) / h, exact to rounding for an
+ * analytic function, h = 1e-30.  grad = (D_x[3], D_k[3]), Dw = dD/domega. */
+static void cp_grad(const om_medium *m, const double *y, double w, double *D, double *grad,
+                    double *Dw)
+{
+    const double h = 1e-30;
+    double complex x[3], k[3];
+    for (int i = 0; i < 3; i++) { x[i] = y[i]; k[i] = y[3 + i]; }
+    *D = creal(cp_D(m, x, k, w));
+    for (int j = 0; j < 6; j++) {
+        double complex xx[3] = {x[0], x[1], x[2]}, kk[3] = {k[0], k[1], k[2]};
+        if (j < 3) xx[j] += I * h; else kk[j - 3] += I * h;
+        grad[j] = cimag(cp_D(m, xx, kk, w)) / h;
+    }
+    *Dw = cimag(cp_D(m, x, k, w + I * h)) / h;
+}
+
+/* ------------------------------------------------------------------------ */
 /* D, ray right-hand side f = (dx/dt, dk/dt) and its Jacobian J = df/dy      */
 /* (y = (x, k), J row-major 2d x 2d).  eqs. (2)-(3).                          */
 
@@ -233,6 +285,11 @@ static double om_D1(const om_medium *m, const double *y, double w)
 {
     int d = m->dim;
     const double *x = y, *k = y + d;
+    if (m->kind == COLDPLASMA) {
+        double D, g[6], Dw;
+        cp_grad(m, y, w, &D, g, &Dw);
+        return D;
+    }
     if (m->kind == ANISO3D) {
         double D = -w * w;
         double kk = 0.0;
@@ -268,6 +325,17 @@ static void om_eval(const om_medium *m, const double *y, double w, double *f, do
     int d = m->dim, n2 = 2 * d;
     const double *x = y, *k = y + d;
     if (J) for (int i = 0; i < n2 * n2; i++) J[i] = 0.0;
+    if (m->kind == COLDPLASMA) {
+        /* eqs. 2-3 with the complex-step partials; no Jacobian (forward only) */
+        double D, g[6], Dw;
+        cp_grad(m, y, w, &D, g, &Dw);
+        for (int i = 0; i < 3; i++) {
+            f[i] = -g[3 + i] / Dw;
+            f[3 + i] = g[i] / Dw;
+        }
+        if (J) for (int i = 0; i < n2 * n2; i++) J[i] = NAN;
+        return;
+    }
     if (m->kind == OLINEAR) {
         /* D = |k|^2 - w^2 + (a + g.x): D_k = 2k, D_w = -2w, D_x = g */
         for (int i = 0; i < d; i++) {

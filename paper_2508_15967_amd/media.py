@@ -76,6 +76,35 @@ def build(med: W.Medium) -> Tuple[rgb.Graph, rgb.Node, List[np.ndarray]]:
                  + (2.0 * m[4]) * (k[1] * k[2]))
             terms.append(g.elem(pid, b) * gb * q)
         D = kk - w2 + _sum(terms)
+    elif med.kind == W.COLDPLASMA:
+        # "Cold Plasma Dispersion Relation": D = Det(eps + n n - n^2 I) (eq. 5)
+        # with n = k/omega (eq. 6, c = 1) and the Stix elements of eqs. 8-10;
+        # eps_12 = -i G is purely imaginary, so the Hermitian determinant is
+        # the real expression M11 M22 M33 - M11 M23^2 - M22 M13^2
+        # - (a^2 + G^2) M33 + 2 a M13 M23 with a = n_x n_y.
+        X = (float(p[0]) * (float(p[1]) * x[0] + 1.0)) / w2
+        Y = float(p[2]) / om
+        den = 1.0 - Y * Y
+        S = 1.0 - X / den
+        G = (Y * X) / den
+        P = 1.0 - X
+        if p[3] > 0:
+            mu = float(p[3])
+            Xi, Yi = X * (1.0 / mu), Y * (-1.0 / mu)
+            deni = 1.0 - Yi * Yi
+            S = S - Xi / deni
+            G = G + (Yi * Xi) / deni
+            P = P - Xi
+        n = [ki / om for ki in k]
+        n2 = _sum([ni * ni for ni in n])
+        M11 = S + n[0] * n[0] - n2
+        M22 = S + n[1] * n[1] - n2
+        M33 = P + n[2] * n[2] - n2
+        a = n[0] * n[1]
+        M13 = n[0] * n[2]
+        M23 = n[1] * n[2]
+        D = (M11 * M22 * M33 - M11 * (M23 * M23) - M22 * (M13 * M13)
+             - (a * a + G * G) * M33 + 2.0 * (a * M13 * M23))
     else:
         raise ValueError(f"unknown medium kind {med.kind}")
     return g, D, params

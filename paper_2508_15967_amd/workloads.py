@@ -42,7 +42,7 @@ from typing import Optional
 import numpy as np
 
 # Medium kinds.  The integer values are part of the oracle's C interface too.
-HOMOG, OLINEAR, LINEARN, LENS2D, STRAT3D, BUMPS3D, SPLINE2D, ANISO3D = range(8)
+HOMOG, OLINEAR, LINEARN, LENS2D, STRAT3D, BUMPS3D, SPLINE2D, ANISO3D, COLDPLASMA = range(9)
 
 RK4, DOPRI54 = 0, 1
 
@@ -69,7 +69,8 @@ class Medium:
                  LINEARN: "N=p0+g.x, g=p1..p3", LENS2D: "n=1+p0 exp(-|x|^2/p1)",
                  STRAT3D: "N=1-p0 exp(1-z'-exp(-z')), z'=(z-p1)/p2",
                  BUMPS3D: "strat3d + sum a_b exp(-|x-c|^2/w^2)",
-                 SPLINE2D: "cubic B-spline N", ANISO3D: "k.A.k-w^2"}
+                 SPLINE2D: "cubic B-spline N", ANISO3D: "k.A.k-w^2",
+                 COLDPLASMA: "Det(eps + nn - n^2 I), w_pe^2 = p0 (p1 x + 1), Omega_e = p2, m_i/m_e = p3"}
         return names[self.kind]
 
 
@@ -350,3 +351,41 @@ def linearn(n_rays: int = 8, seed: int = 13, dt: float = 1e-2, t_end: float = 4.
     med = Medium(LINEARN, 3, p=np.array([a, g[0], g[1], g[2], 0, 0, 0, 0.0]))
     return Workload("linearn", "l", 3, med, x0, k0, omega, RK4, dt=dt,
                     n_steps=int(round(t_end / dt)))
+
+
+# ---------------------------------------------------------------------------
+# cold plasma (eqs. 5-10) in a slab: B along z, electron density following the
+# linear profile f(x) = 0.1 x + 1 of eq. 4; omega, c = 1 units
+
+def _stix(med, x, w):
+    """Stix S, D, P at positions x for frequency w (electrons, optional ions)."""
+    wpe2 = med.p[0] * (med.p[1] * x + 1.0)
+    Xe, Ye = wpe2 / w ** 2, med.p[2] / w
+    S = 1.0 - Xe / (1.0 - Ye ** 2)
+    Dst = Ye * Xe / (1.0 - Ye ** 2)
+    P = 1.0 - Xe
+    if med.p[3] > 0:
+        Xi, Yi = Xe / med.p[3], -Ye / med.p[3]
+        S = S - Xi / (1.0 - Yi ** 2)
+        Dst = Dst + Yi * Xi / (1.0 - Yi ** 2)
+        P = P - Xi
+    return S, Dst, P
+
+
+def coldplasma(mode: str = "O", n_rays: int = 64, seed: int = 14, x0: float = -5.0,
+               direction: float = 1.0, dt: float = 1e-2, n_steps: int = 2000) -> Workload:
+    """Rays in the xy-plane (k_z = 0, perpendicular to B) launched on the O- or
+    X-mode branch.  Profile: X = w_pe^2/w^2 = 0.5 (0.1 x + 1), |Omega_e| = 0.5 w,
+    so the O cut-off (X = 1) is at x = 10, the upper-hybrid resonance
+    (X = 0.75) at x = 5, the R cut-off (X = 0.5) at x = 0 and the L cut-off
+    (X = 1.5) at x = 20."""
+    rng = np.random.default_rng(seed)
+    med = Medium(COLDPLASMA, 3, p=np.array([0.5, 0.1, -0.5, 0.0, 0, 0, 0, 0.0]))
+    x = np.stack([np.full(n_rays, x0), rng.uniform(-1, 1, n_rays), np.zeros(n_rays)])
+    w = np.ones(n_rays)
+    S, Dst, P = _stix(med, x[0], w)
+    n2 = P if mode == "O" else (S * S - Dst * Dst) / S   # perpendicular: P or RL/S
+    ky = rng.uniform(-0.1, 0.1, n_rays) * np.sqrt(np.abs(n2))
+    kx = direction * np.sqrt(n2 * w ** 2 - ky ** 2)
+    k = np.stack([kx, ky, np.zeros(n_rays)])
+    return Workload(f"coldplasma_{mode}", "c" + mode, 3, med, x, k, w, RK4, dt=dt, n_steps=n_steps)

@@ -48,8 +48,36 @@ def N_of(med, x):
     raise ValueError(med.kind)
 
 
+def _coldplasma_D(med, x, k, w):
+    """Det(eps + n n - n^2 I) with eps from eqs. 7-10, expanded with complex
+    entries and the imaginary unit kept explicit (the result is real)."""
+    X = med.p[0] * (med.p[1] * x[0] + 1.0) / (w * w)
+    Y = med.p[2] / w
+    S = 1 - X / (1 - Y * Y)
+    e12 = -1j * (Y * X / (1 - Y * Y))
+    P = 1 - X
+    if med.p[3] > 0:
+        Xi, Yi = X / med.p[3], -Y / med.p[3]
+        S = S - Xi / (1 - Yi * Yi)
+        e12 = e12 - 1j * (Yi * Xi / (1 - Yi * Yi))
+        P = P - Xi
+    n = [k[i] / w for i in range(3)]
+    n2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2]
+    # full 3x3 complex determinant by cofactors (entries may carry a
+    # complex-step perturbation, so no conjugation is used)
+    m = [[S + n[0] * n[0] - n2, e12 + n[0] * n[1], n[0] * n[2]],
+         [-e12 + n[1] * n[0], S + n[1] * n[1] - n2, n[1] * n[2]],
+         [n[2] * n[0], n[2] * n[1], P + n[2] * n[2] - n2]]
+    det = (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1])
+           - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+           + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
+    return det
+
+
 def D_of(med, x, k, w):
     """D for every medium kind; arrays (dim, n), w shape (n,)."""
+    if med.kind == W.COLDPLASMA:
+        return _coldplasma_D(med, x, k, w)
     if med.kind == W.ANISO3D:
         D = (k * k).sum(0) - w * w
         for b in range(len(med.scales)):
@@ -65,8 +93,30 @@ def D_of(med, x, k, w):
     return (k * k).sum(0) - w * w * N_of(med, x)
 
 
+def rhs_central_diff(med, y, w, h=1e-6):
+    """Ray right-hand side from central differences of Re D (for the cold
+    plasma, whose explicit-i determinant leaves rounding-level imaginary
+    parts that would swamp a complex step)."""
+    d = y.shape[0] // 2
+    n = y.shape[1]
+    wv = np.asarray(w, dtype=float) * np.ones(n)
+    Dr = lambda yy, ww: np.real(D_of(med, yy[:d], yy[d:], ww))
+    grads = np.zeros((2 * d, n))
+    for i in range(2 * d):
+        e = np.zeros_like(y)
+        e[i] = h
+        grads[i] = (Dr(y + e, wv) - Dr(y - e, wv)) / (2 * h)
+    Dw = (Dr(y, wv + h) - Dr(y, wv - h)) / (2 * h)
+    f = np.empty((2 * d, n))
+    f[:d] = -grads[d:] / Dw
+    f[d:] = grads[:d] / Dw
+    return f
+
+
 def rhs_complex_step(med, y, w, h=1e-30):
     """Ray right-hand side from complex-step partials of D."""
+    if med.kind == W.COLDPLASMA:
+        return rhs_central_diff(med, y, w)
     d = y.shape[0] // 2
     n = y.shape[1]
     yc = y.astype(np.complex128)

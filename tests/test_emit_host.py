@@ -86,10 +86,11 @@ def _points(w, n, rng):
     return np.ascontiguousarray(y), np.ascontiguousarray(w.omega[idx])
 
 
-@pytest.mark.parametrize("cfg", ["1", "2", "3", "4", "5"])
+@pytest.mark.parametrize("cfg", ["1", "2", "3", "4", "5", "cO", "cX"])
 def test_emitted_functions_match_oracle(oracle, cfg):
     from paper_2508_15967_amd import media
-    w = W.make(cfg, 2048)
+    w = {"cO": lambda: W.coldplasma("O"), "cX": lambda: W.coldplasma("X", x0=12.0)}.get(
+        cfg, lambda: W.make(cfg, 2048))()
     g, D, params = media.build(w.medium)
     adj = cfg in ("4", "5")
     prog = g.compile(D, want_adjoint=adj, compile_only=True)
@@ -109,7 +110,9 @@ def test_emitted_functions_match_oracle(oracle, cfg):
                       C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
         fo, Do, J = oracle.eval_points(w.medium, y, om, jac=True)
         scale = np.abs(fo).max(axis=0)
-        assert (np.abs(f - fo).max(axis=0) / scale).max() < 1e-13
+        # the oracle's cold-plasma partials are complex-step derivatives of
+        # its own D: agreement to rounding of the two derivative routes
+        assert (np.abs(f - fo).max(axis=0) / scale).max() < (1e-12 if cfg.startswith("c") else 1e-13)
         assert np.abs(Dv - Do).max() < 1e-13 * (1 + np.abs(Do).max())
         if adj:
             v = np.ascontiguousarray(rng.standard_normal((ny, n)))

@@ -1,0 +1,61 @@
+"""The paper's own physics on the GPU: the cold-plasma dispersion relation
+D = Det(eps + n n - n^2 I) (eqs. 5-10) in a slab with the eq. 4 density
+profile, B along z, perpendicular propagation.  All partial derivatives
+(including dD/domega) come from the graph compiler; the oracle's come from
+complex-step differentiation of its own D.
+
+Profile X = w_pe^2/w^2 = 0.5 (0.1 x + 1), |Omega_e| = w/2: R cut-off x = 0,
+upper-hybrid resonance x = 5, O (plasma) cut-off x = 10, L cut-off x = 20.
+"""
+import numpy as np
+import pytest
+
+from paper_2508_15967_amd import workloads as W
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def test_O_mode_parity_and_cutoff(oracle):
+    """O-mode from x = -5 crosses the upper-hybrid layer, turns at the plasma
+    cut-off x = 10 (eq. 4 parabola) and comes back: GPU = oracle = parabola."""
+    w = W.coldplasma("O", n_rays=256, dt=1e-2, n_steps=4000)
+    w.store_every = 100
+    g = U.gpu_trace(w, store=True, store_D=True)
+    o = oracle.trace(w, store=True)
+    ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    xmax = g["traj"][:, 0].max(0)
+    kperp2 = w.k0[1] ** 2
+    x_turn = (w.omega ** 2 - kperp2 - 0.5) / 0.05     # w^2 - k_y^2 = w_pe^2(x)
+    assert np.abs(xmax - x_turn).max() < 1e-3 and xmax.min() > 5.0
+    assert np.abs(g["traj_D"]).max() < 1e-12   # rays stay on the dispersion surface (eq. 1)
+
+
+def test_X_mode_passes_plasma_cutoff_stalls_at_upper_hybrid(oracle):
+    """X-mode launched at x = 12 toward lower density crosses the O-mode's
+    plasma cut-off x = 10 and approaches the upper-hybrid resonance x = 5
+    with growing |k| without crossing it."""
+    w = W.coldplasma("X", n_rays=256, x0=12.0, direction=-1.0, dt=1e-2, n_steps=6000)
+    w.store_every = 500
+    g = U.gpu_trace(w, store=True)
+    o = oracle.trace(w, store=True)
+    ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
+    assert ex < 1e-10 and ek < 1e-10, (ex, ek)   # |k| grows toward the resonance
+    x = g["traj"][:, 0]
+    assert np.all(x[-1] < 10.0) and np.all(x[-1] > 5.0)
+    kk = np.linalg.norm(g["traj"][:, 3:], axis=1)
+    assert np.all(kk[-1] > 2.0 * kk[0])
+    assert np.all(np.diff(x, axis=0) < 0)        # monotone approach, no reflection
+
+
+def test_X_mode_reflects_at_L_cutoff(oracle):
+    w = W.coldplasma("X", n_rays=256, x0=12.0, direction=1.0, dt=1e-2, n_steps=6000)
+    w.store_every = 100
+    g = U.gpu_trace(w, store=True)
+    o = oracle.trace(w, store=True)
+    ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    x = g["traj"][:, 0]
+    assert np.all(x.max(0) < 20.0) and np.all(x.max(0) > 19.5)
+    assert np.all(g["k"][0] < 0)                 # turned around

@@ -105,16 +105,20 @@ def test_linearn_closed_form(oracle):
 MEDIA = ["1", "2", "3", "4", "5"]
 
 
-@pytest.mark.parametrize("cfg", MEDIA + ["homog", "olinear", "linearn"])
+@pytest.mark.parametrize("cfg", MEDIA + ["homog", "olinear", "linearn", "coldO", "coldX"])
 def test_rhs_matches_complex_step_of_D(oracle, cfg):
-    w = {"homog": W.homog, "olinear": W.olinear, "linearn": W.linearn}.get(
+    w = {"homog": W.homog, "olinear": W.olinear, "linearn": W.linearn,
+         "coldO": lambda: W.coldplasma("O"), "coldX": lambda: W.coldplasma("X", x0=12.0)}.get(
         cfg, lambda: W.make(cfg, 4096))()
     rng = np.random.default_rng(100)
     y, om = _random_states(w, 500, rng)
+    if cfg.startswith("cold"):
+        y[5] = 0.3 * rng.uniform(-1, 1, y.shape[1])  # oblique k_z as well
     f, D, _ = oracle.eval_points(w.medium, y, om)
     fr = DD.rhs_complex_step(w.medium, y, om)
     scale = np.abs(fr).max(axis=0) + 1e-300
-    assert (np.abs(f - fr).max(axis=0) / scale).max() < 1e-13
+    tol = 1e-7 if cfg.startswith("cold") else 1e-13   # central differences there
+    assert (np.abs(f - fr).max(axis=0) / scale).max() < tol
     Dr = np.real(DD.D_of(w.medium, y[: w.dim], y[w.dim:], om))
     assert np.abs(D - Dr).max() < 1e-13 * (1 + np.abs(Dr).max())
 
@@ -443,3 +447,26 @@ def test_newton_launch_conditions_closed_form(oracle):
         err = np.abs(k[0][conv] - exact[conv])
         assert np.all(err <= 1e-14 * np.abs(exact[conv]) + 4e-15 / (2 * np.abs(exact[conv])))
         assert np.abs(D[conv]).max() <= 1e-15
+
+
+def test_coldplasma_O_mode_follows_eq4_parabola(oracle):
+    """Perpendicular O-mode rays of the full cold-plasma D: D factors as
+    F * (P - n^2) with F != 0 along the path, so the rays are those of
+    D = |k|^2 - w^2 + w_pe^2(x), w_pe^2 = 0.5 + 0.05 x (eq. 4 profile):
+    parabolas that turn at the O cut-off x = 10 after crossing the
+    upper-hybrid layer x = 5.  RK4 is exact for the parabola, and on the
+    full D its off-shell stage points move the result by far less than the
+    closed form's rounding, so every step size reproduces the parabola."""
+    errs = []
+    for dt, steps in ((4e-2, 1000), (2e-2, 2000), (1e-2, 4000)):
+        w = W.coldplasma("O", n_rays=16, dt=dt, n_steps=steps)
+        r = oracle.trace(w)
+        T = dt * steps
+        g = np.array([0.05, 0.0, 0.0])[:, None]
+        ke = w.k0 - g * T / (2 * w.omega)
+        xe = w.x0 + w.k0 * T / w.omega - g * T * T / (4 * w.omega ** 2)
+        errs.append(max(np.abs(r["x"] - xe).max(), np.abs(r["k"] - ke).max()))
+        assert np.all(r["status"] == oracle.RAY_OK)
+    # the rays turned around (k_x < 0 at T = 40, turning at x = 10)
+    assert np.all(r["k"][0] < 0)
+    assert max(errs) < 1e-10, errs
