@@ -3,6 +3,8 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
+#include <algorithm>
 #include <map>
 #include <sstream>
 #include <stdexcept>
@@ -53,11 +55,25 @@ struct Emitter {
         bool emitted = false;
     };
     std::vector<Group> groups;
+    // Chains of single-use additions/subtractions become accumulations whose
+    // terms may be added in any order (see schedule()).
+    struct Chain {
+        uint32_t root;
+        std::vector<std::pair<uint32_t, int>> leaves;  // term node, sign
+        bool started = false;
+    };
+    std::vector<Chain> chains;
+    std::vector<int> chain_of_root;  // node -> chain index or -1
+    std::vector<char> interior;      // node folded into a chain
+    std::vector<uint32_t> consumer;  // unique consumer of a single-use node
 
     Emitter(const Graph &g_, const std::vector<int> &ts) : g(g_), table_slot(ts) {
         uses.assign(g.size(), 0);
         fused.assign(g.size(), 0);
         emitted.assign(g.size(), 0);
+        chain_of_root.assign(g.size(), -1);
+        interior.assign(g.size(), 0);
+        consumer.assign(g.size(), NONE);
     }
 
     std::string name(uint32_t n) const {
@@ -111,13 +127,52 @@ struct Emitter {
             if (nd.a != NONE) uses[nd.a]++;
             if (nd.b != NONE) uses[nd.b]++;
         }
-        for (uint32_t r : roots) uses[r]++;
+        std::vector<char> is_root(g.size(), 0);
+        for (uint32_t r : roots) {
+            uses[r]++;
+            is_root[r] = 1;
+        }
         for (uint32_t n : order) {
             const Node &nd = g.node(n);
-            if (nd.op == ADD || nd.op == SUB) {
-                if (fusable_mul(nd.a) && !fused[nd.a]) fused[nd.a] = 1;
-                else if (fusable_mul(nd.b) && !fused[nd.b]) fused[nd.b] = 1;
+            if (nd.a != NONE && uses[nd.a] == 1) consumer[nd.a] = n;
+            if (nd.b != NONE && uses[nd.b] == 1) consumer[nd.b] = n;
+        }
+        auto addsub = [&](uint32_t n) { return g.node(n).op == ADD || g.node(n).op == SUB; };
+        for (uint32_t n : order)
+            if (addsub(n) && uses[n] == 1 && !is_root[n] && consumer[n] != NONE && addsub(consumer[n]))
+                interior[n] = 1;
+        // chain roots: additions with at least one interior operand
+        for (uint32_t n : order) {
+            if (!addsub(n) || interior[n]) continue;
+            const Node &nd = g.node(n);
+            if (!interior[nd.a] && !interior[nd.b]) {
+                // plain two-operand addition: fuse one single-use product
+                if (fusable_mul(nd.a)) fused[nd.a] = 1;
+                else if (fusable_mul(nd.b)) fused[nd.b] = 1;
+                continue;
             }
+            Chain c;
+            c.root = n;
+            std::vector<std::pair<uint32_t, int>> stack{{n, 1}};
+            while (!stack.empty()) {
+                auto [m, sg] = stack.back();
+                stack.pop_back();
+                const Node &md = g.node(m);
+                auto push = [&](uint32_t o, int so) {
+                    if (interior[o]) stack.push_back({o, so});
+                    else c.leaves.push_back({o, so});
+                };
+                // right operand first so that leaves come out in left-to-right order
+                push(md.b, md.op == SUB ? -sg : sg);
+                push(md.a, sg);
+            }
+            for (auto &lf : c.leaves)
+                if (fusable_mul(lf.first)) fused[lf.first] = 1;
+            chain_of_root[n] = (int)chains.size();
+            chains.push_back(std::move(c));
+        }
+        for (uint32_t n : order) {
+            const Node &nd = g.node(n);
             if (nd.op == SPLINE) {
                 uint32_t def = (uint32_t)nd.val;
                 int gi = -1;
@@ -199,7 +254,7 @@ struct Emitter {
         }
         default: break;
         }
-        if (fused[n]) return;  // emitted inside its consumer
+        if (fused[n] || interior[n] || chain_of_root[n] >= 0) return;  // emitted elsewhere
         std::string A = nd.a != NONE ? name(nd.a) : "", B = nd.b != NONE ? name(nd.b) : "";
         std::string e;
         switch (nd.op) {
@@ -248,6 +303,184 @@ struct Emitter {
             throw std::logic_error("emit: unexpected node");
         }
         os << "  const double " << name(n) << " = " << e << ";\n";
+    }
+
+    // One term of a chain: the first defines the accumulator, the others
+    // add to it (an fma when the term is a single-use product).
+    void emit_acc(int ci, size_t li) {
+        Chain &c = chains[ci];
+        const uint32_t leaf = c.leaves[li].first;
+        const int sg = c.leaves[li].second;
+        const std::string R = name(c.root);
+        const bool prod = fused[leaf] && g.node(leaf).op == MUL;
+        if (!c.started) {
+            c.started = true;
+            std::string t;
+            if (prod) {
+                const Node &m = g.node(leaf);
+                t = std::string(sg < 0 ? "-" : "") + name(m.a) + " * " + name(m.b);
+                count(MUL);
+            } else {
+                t = std::string(sg < 0 ? "-" : "") + name(leaf);
+            }
+            os << "  double " << R << " = " << t << ";\n";
+            return;
+        }
+        if (prod) {
+            const Node &m = g.node(leaf);
+            os << "  " << R << " = fma(" << (sg < 0 ? "-" : "") << name(m.a) << ", " << name(m.b) << ", " << R
+               << ");\n";
+            count_fma();
+        } else {
+            os << "  " << R << " = " << R << (sg < 0 ? " - " : " + ") << name(leaf) << ";\n";
+            count(ADD);
+        }
+    }
+
+    // Register-pressure-aware order (greedy list scheduling) over three kinds
+    // of units: a node, one term of a chain, and a chain's completion.  Among
+    // the units whose inputs are available, take the one that adds the fewest
+    // live values: +1 for a new value (a chain's first term creates its
+    // accumulator), -1 for every input it is the last user of.  Ties go to the
+    // unit that continues the most recently computed value, then to the lower
+    // node index.  A sum over many similar terms (16 Gaussian blobs, in a
+    // vector-Jacobian product with 6 outputs) is thereby accumulated term by
+    // term as its inputs appear, instead of keeping every term's shared
+    // values alive until one long chain reaches them.  Only independent
+    // operations move; sums are reassociated (deterministically).
+    void schedule_and_emit(const std::vector<uint32_t> &order, const std::vector<uint32_t> &roots) {
+        const size_t N = g.size();
+        enum { U_NODE, U_ACC, U_FIN };
+        struct Unit {
+            int kind;
+            uint32_t node;
+            int chain;
+            size_t leaf;
+            std::vector<uint32_t> vals;  // input values
+        };
+        std::vector<Unit> units;
+        std::vector<int> def_unit(N, -1);
+        auto inputs = [&](uint32_t m, std::vector<uint32_t> &out) {
+            if (m == NONE) return;
+            const Node &md = g.node(m);
+            if (md.op == CONST || md.op == VAR) return;
+            if (fused[m]) {
+                for (uint32_t o : {md.a, md.b})
+                    if (o != NONE && g.node(o).op != CONST && g.node(o).op != VAR) out.push_back(o);
+                return;
+            }
+            out.push_back(m);
+        };
+        for (uint32_t n : order) {
+            const Node &nd = g.node(n);
+            if (nd.op == CONST || nd.op == VAR || fused[n] || interior[n]) continue;
+            int ci = chain_of_root[n];
+            if (ci >= 0) {
+                std::vector<int> accs;
+                for (size_t li = 0; li < chains[ci].leaves.size(); li++) {
+                    Unit u{U_ACC, n, ci, li, {}};
+                    uint32_t leaf = chains[ci].leaves[li].first;
+                    if (fused[leaf]) inputs(leaf, u.vals);
+                    else if (g.node(leaf).op != CONST && g.node(leaf).op != VAR) u.vals.push_back(leaf);
+                    accs.push_back((int)units.size());
+                    units.push_back(std::move(u));
+                }
+                Unit f{U_FIN, n, ci, 0, {}};
+                def_unit[n] = (int)units.size();
+                units.push_back(std::move(f));
+                continue;
+            }
+            Unit u{U_NODE, n, -1, 0, {}};
+            if (nd.op == ADD || nd.op == SUB || nd.op != SPLINE) {
+                inputs(nd.a, u.vals);
+                inputs(nd.b, u.vals);
+            }
+            if (nd.op == SPLINE) {
+                inputs(nd.a, u.vals);
+                inputs(nd.b, u.vals);
+            }
+            def_unit[n] = (int)units.size();
+            units.push_back(std::move(u));
+        }
+        const size_t U = units.size();
+        std::vector<std::vector<int>> succ(U);
+        std::vector<int> unmet(U, 0);
+        std::vector<int> remaining(N, 0);
+        for (size_t i = 0; i < U; i++) {
+            Unit &u = units[i];
+            std::sort(u.vals.begin(), u.vals.end());
+            u.vals.erase(std::unique(u.vals.begin(), u.vals.end()), u.vals.end());
+            for (uint32_t v : u.vals) {
+                remaining[v]++;
+                succ[def_unit[v]].push_back((int)i);
+                unmet[i]++;
+            }
+        }
+        // a chain completes after all its terms
+        for (size_t i = 0; i < U; i++)
+            if (units[i].kind == U_ACC) {
+                succ[i].push_back(def_unit[units[i].node]);
+                unmet[def_unit[units[i].node]]++;
+            }
+        for (uint32_t r : roots)
+            if (r != NONE && def_unit.size() > r && def_unit[r] >= 0) remaining[r]++;
+        std::vector<int> when(N, -1);
+        std::vector<char> started(chains.size(), 0);
+        std::vector<int> ready;
+        for (size_t i = 0; i < U; i++)
+            if (unmet[i] == 0) ready.push_back((int)i);
+        int step = 0, live = 0, max_live = 0;
+        bool step_started_new = false;
+        while (!ready.empty()) {
+            step_started_new = false;
+            size_t best = 0;
+            long best_cost = 1L << 40;
+            int best_recent = -2;
+            for (size_t r = 0; r < ready.size(); r++) {
+                const Unit &u = units[ready[r]];
+                long cost;
+                int recent = -1;  // priority among equal cost: larger is better
+                if (u.kind == U_FIN) {
+                    cost = -1000;
+                } else {
+                    cost = (u.kind == U_NODE) ? (remaining[u.node] > 0 ? 1 : 0) : (started[u.chain] ? 0 : 1);
+                    for (uint32_t v : u.vals) {
+                        if (remaining[v] == 1) cost--;
+                        recent = std::max(recent, when[v]);
+                    }
+                }
+                const Unit &b = units[ready[best]];
+                if (cost < best_cost || (cost == best_cost && recent > best_recent) ||
+                    (cost == best_cost && recent == best_recent && u.node < b.node)) {
+                    best = r;
+                    best_cost = cost;
+                    best_recent = recent;
+                }
+            }
+            const int ui = ready[best];
+            ready[best] = ready.back();
+            ready.pop_back();
+            const Unit &u = units[ui];
+            if (u.kind == U_NODE) {
+                emit_node(u.node);
+                when[u.node] = step++;
+            } else if (u.kind == U_ACC) {
+                step_started_new = !started[u.chain];
+                emit_acc(u.chain, u.leaf);
+                started[u.chain] = 1;
+                when[u.node] = step++;
+            } else {
+                emitted[u.node] = 1;
+            }
+            for (uint32_t v : u.vals)
+                if (--remaining[v] == 0) live--;
+            if ((u.kind == U_NODE && remaining[u.node] > 0) || (u.kind == U_ACC && step_started_new)) live++;
+            max_live = std::max(max_live, live);
+            for (int sidx : succ[ui])
+                if (--unmet[sidx] == 0) ready.push_back(sidx);
+        }
+        if (std::getenv("RG_DEBUG_SCHED"))
+            std::fprintf(stderr, "schedule: %zu units, %zu chains, max live %d\n", U, chains.size(), max_live);
     }
 
     // Gradient scatter of spline coefficients: for each cell group, the 16
@@ -323,7 +556,7 @@ std::string emit_function(const Graph &g, const FunctionSpec &spec,
     std::vector<uint32_t> order = g.reachable(roots);
     em.plan(order, roots);
     em.os << spec.signature << "\n";
-    for (uint32_t n : order) em.emit_node(n);
+    em.schedule_and_emit(order, roots);
     if (!spec.spline_seeds.empty()) em.emit_spline_grads(spec.spline_seeds);
     for (const Output &o : spec.outputs) {
         if (spec.returns_value) {
