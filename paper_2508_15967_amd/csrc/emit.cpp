@@ -348,7 +348,22 @@ struct Emitter {
     // term as its inputs appear, instead of keeping every term's shared
     // values alive until one long chain reaches them.  Only independent
     // operations move; sums are reassociated (deterministically).
-    void schedule_and_emit(const std::vector<uint32_t> &order, const std::vector<uint32_t> &roots) {
+    // One output statement ("lhs = v;" or "lhs += v;").
+    void emit_output(const Output &o) {
+        if (o.accumulate) {
+            if (!g.is_const(o.node, 0.0)) {
+                os << "  " << o.lhs << " += " << name(o.node) << ";\n";
+                count_plain(1);
+            }
+        } else {
+            os << "  " << o.lhs << " = " << name(o.node) << ";\n";
+        }
+    }
+
+    // `outs` (may be null) are written as soon as their value is complete,
+    // so that a value kept only for an output dies there.
+    void schedule_and_emit(const std::vector<uint32_t> &order, const std::vector<uint32_t> &roots,
+                           const std::vector<Output> *outs, std::vector<char> *out_done) {
         const size_t N = g.size();
         enum { U_NODE, U_ACC, U_FIN };
         struct Unit {
@@ -391,14 +406,8 @@ struct Emitter {
                 continue;
             }
             Unit u{U_NODE, n, -1, 0, {}};
-            if (nd.op == ADD || nd.op == SUB || nd.op != SPLINE) {
-                inputs(nd.a, u.vals);
-                inputs(nd.b, u.vals);
-            }
-            if (nd.op == SPLINE) {
-                inputs(nd.a, u.vals);
-                inputs(nd.b, u.vals);
-            }
+            inputs(nd.a, u.vals);
+            inputs(nd.b, u.vals);
             def_unit[n] = (int)units.size();
             units.push_back(std::move(u));
         }
@@ -424,19 +433,89 @@ struct Emitter {
             }
         for (uint32_t r : roots)
             if (r != NONE && def_unit.size() > r && def_unit[r] >= 0) remaining[r]++;
+        // Phases.  In a sum over many exponentials (Gaussian blobs) most
+        // units depend on at most one of them, so the units can run group
+        // by group: each unit gets the set of exponentials it depends on and
+        // a level, the number of reductions over several groups (a value
+        // that depends on two or more) on its longest input path.  Units
+        // then run level by level and, within a level, group by group, with
+        // the units that need several groups last.  A unit that depends on
+        // no exponential runs in the first phase of its consumers, just
+        // before its first use.  An exponential of an expression that
+        // already holds one (a double exponential) joins the inner one's
+        // group.  Phases never fall along an edge, so every phase completes
+        // before the next begins.
+        std::vector<int> phase(U, 0);
+        {
+            std::vector<uint64_t> mask(U, 0);
+            std::vector<int> lev(U, 0);
+            std::vector<std::vector<int>> pred(U);
+            for (size_t i = 0; i < U; i++)
+                for (int c : succ[i]) pred[c].push_back((int)i);
+            auto multi = [](uint64_t m) { return (m & (m - 1)) != 0; };
+            int nexp = 0;
+            for (size_t i = 0; i < U; i++) {
+                for (int v : pred[i]) {
+                    if (multi(mask[v])) {
+                        lev[i] = std::max(lev[i], lev[v] + 1);
+                    } else {
+                        lev[i] = std::max(lev[i], lev[v]);
+                        mask[i] |= mask[v];
+                    }
+                }
+                if (units[i].kind == U_NODE && g.node(units[i].node).op == EXP && mask[i] == 0) {
+                    if (nexp < 64) mask[i] = 1ull << nexp;
+                    nexp++;
+                }
+            }
+            if (nexp >= 4 && nexp <= 64) {
+                const int per = nexp + 2;
+                for (size_t i = U; i-- > 0;) {
+                    if (mask[i] == 0) {
+                        int ph = 1 << 30;
+                        for (int c : succ[i]) ph = std::min(ph, phase[c]);
+                        phase[i] = succ[i].empty() ? lev[i] * per : ph;
+                    } else if (multi(mask[i])) {
+                        phase[i] = lev[i] * per + nexp + 1;
+                    } else {
+                        phase[i] = lev[i] * per + 1 + __builtin_ctzll(mask[i]);
+                    }
+                }
+                // a unit's phase is at least its inputs'
+                for (size_t i = 0; i < U; i++)
+                    for (int c : succ[i]) phase[c] = std::max(phase[c], phase[i]);
+                if (std::getenv("RG_DEBUG_SCHED")) {
+                    std::map<int, int> h;
+                    for (size_t i = 0; i < U; i++) h[phase[i]]++;
+                    std::fprintf(stderr, "phases:");
+                    for (auto &kv : h) std::fprintf(stderr, " %d:%d", kv.first, kv.second);
+                    std::fprintf(stderr, "\n");
+                }
+            }
+        }
         std::vector<int> when(N, -1);
         std::vector<char> started(chains.size(), 0);
         std::vector<int> ready;
         for (size_t i = 0; i < U; i++)
             if (unmet[i] == 0) ready.push_back((int)i);
-        int step = 0, live = 0, max_live = 0;
+        int step = 0, live = 0, max_live = 0, cur_phase = 0;
         bool step_started_new = false;
         while (!ready.empty()) {
             step_started_new = false;
+            // stay in the current phase while it has ready units
+            int lowest = 1 << 30;
+            for (int r : ready) lowest = std::min(lowest, phase[r]);
+            cur_phase = std::max(cur_phase, lowest);
             size_t best = 0;
             long best_cost = 1L << 40;
             int best_recent = -2;
+            bool have = false;
             for (size_t r = 0; r < ready.size(); r++) {
+                if (phase[ready[r]] > cur_phase) continue;
+                if (!have) {
+                    best = r;
+                    have = true;
+                }
                 const Unit &u = units[ready[r]];
                 long cost;
                 int recent = -1;  // priority among equal cost: larger is better
@@ -475,6 +554,13 @@ struct Emitter {
             for (uint32_t v : u.vals)
                 if (--remaining[v] == 0) live--;
             if ((u.kind == U_NODE && remaining[u.node] > 0) || (u.kind == U_ACC && step_started_new)) live++;
+            if (outs && u.kind != U_ACC && remaining[u.node] > 0)
+                for (size_t oi = 0; oi < outs->size(); oi++)
+                    if (!(*out_done)[oi] && (*outs)[oi].node == u.node) {
+                        emit_output((*outs)[oi]);
+                        (*out_done)[oi] = 1;
+                        if (--remaining[u.node] == 0) live--;
+                    }
             max_live = std::max(max_live, live);
             for (int sidx : succ[ui])
                 if (--unmet[sidx] == 0) ready.push_back(sidx);
@@ -556,19 +642,13 @@ std::string emit_function(const Graph &g, const FunctionSpec &spec,
     std::vector<uint32_t> order = g.reachable(roots);
     em.plan(order, roots);
     em.os << spec.signature << "\n";
-    em.schedule_and_emit(order, roots);
+    std::vector<char> out_done(spec.outputs.size(), 0);
+    em.schedule_and_emit(order, roots, spec.returns_value ? nullptr : &spec.outputs, &out_done);
     if (!spec.spline_seeds.empty()) em.emit_spline_grads(spec.spline_seeds);
-    for (const Output &o : spec.outputs) {
-        if (spec.returns_value) {
-            em.os << "  return " << em.name(o.node) << ";\n";
-        } else if (o.accumulate) {
-            if (!g.is_const(o.node, 0.0)) {
-                em.os << "  " << o.lhs << " += " << em.name(o.node) << ";\n";
-                em.count_plain(1);
-            }
-        } else {
-            em.os << "  " << o.lhs << " = " << em.name(o.node) << ";\n";
-        }
+    for (size_t oi = 0; oi < spec.outputs.size(); oi++) {
+        const Output &o = spec.outputs[oi];
+        if (spec.returns_value) em.os << "  return " << em.name(o.node) << ";\n";
+        else if (!out_done[oi]) em.emit_output(o);
     }
     em.os << "}\n";
     if (flops) *flops = em.fl;

@@ -256,6 +256,64 @@ uint32_t Graph::df(uint32_t f, uint32_t wrt) {
     return d[f];
 }
 
+// Reverse mode: adjoints flow from each node to its operands in decreasing
+// index order (a node's consumers all have larger indices, so its adjoint is
+// complete when it is reached).  Contributions are summed with the reducing
+// factories, so zero terms vanish and shared sub-expressions are reused.
+std::vector<uint32_t> Graph::adjoints(const std::vector<uint32_t> &outs,
+                                      const std::vector<uint32_t> &seeds) {
+    std::vector<uint32_t> order = reachable(outs);
+    std::vector<uint32_t> adj(nodes_.size(), NONE);
+    auto acc = [&](uint32_t n, uint32_t c) {
+        if (n == NONE || is_const(c, 0.0)) return;
+        if (adj.size() <= n) adj.resize(nodes_.size(), NONE);
+        adj[n] = adj[n] == NONE ? c : add(adj[n], c);
+    };
+    for (size_t i = 0; i < outs.size(); i++) acc(outs[i], seeds[i]);
+    for (size_t oi = order.size(); oi-- > 0;) {
+        const uint32_t n = order[oi];
+        if (adj.size() < nodes_.size()) adj.resize(nodes_.size(), NONE);
+        const uint32_t a = adj[n];
+        if (a == NONE) continue;
+        const Node nd = nodes_[n];  // copy: factories may grow nodes_
+        switch (nd.op) {
+        case CONST: case VAR: case PARAM:
+            break;
+        case ADD: acc(nd.a, a); acc(nd.b, a); break;
+        case SUB: acc(nd.a, a); acc(nd.b, neg(a)); break;
+        case MUL: acc(nd.a, mul(a, nd.b)); acc(nd.b, mul(a, nd.a)); break;
+        case DIV:
+            // n = a/b: dn/da = 1/b, dn/db = -n/b;  (1/b): -(1/b)^2
+            if (is_const(nd.a, 1.0)) {
+                acc(nd.b, neg(mul(a, mul(n, n))));
+            } else {
+                const uint32_t q = div(a, nd.b);
+                acc(nd.a, q);
+                acc(nd.b, neg(mul(q, n)));
+            }
+            break;
+        case NEG: acc(nd.a, neg(a)); break;
+        case EXP: acc(nd.a, mul(a, n)); break;
+        case LOG: acc(nd.a, div(a, nd.a)); break;
+        case SQRT: acc(nd.a, div(mul(constant(0.5), a), n)); break;
+        case SIN: acc(nd.a, mul(a, unary(COS, nd.a))); break;
+        case COS: acc(nd.a, neg(mul(a, unary(SIN, nd.a)))); break;
+        case POWI:
+            acc(nd.a, mul(a, mul(constant((double)nd.aux), powi(nd.a, nd.aux - 1))));
+            break;
+        case SPLINE: {
+            const int du = nd.aux / 4, dv = nd.aux % 4;
+            const uint32_t def = (uint32_t)nd.val;
+            acc(nd.a, mul(a, spline(def, du + 1, dv, nd.a, nd.b)));
+            acc(nd.b, mul(a, spline(def, du, dv + 1, nd.a, nd.b)));
+            break;
+        }
+        }
+    }
+    adj.resize(nodes_.size(), NONE);
+    return adj;
+}
+
 // -------------------------------------------------------------- evaluate ---
 
 void bspline_weights(int order, double u, double w[4]) {

@@ -72,6 +72,12 @@ public:
     // d f / d wrt by the chain rule; wrt may be any node (treated as a leaf).
     uint32_t df(uint32_t f, uint32_t wrt);
 
+    // Reverse-mode derivative of s = sum_i seeds[i] * outs[i]: the adjoint
+    // ds/dn of every node n that s depends on (NONE where it is zero),
+    // indexed by node.
+    std::vector<uint32_t> adjoints(const std::vector<uint32_t> &outs,
+                                   const std::vector<uint32_t> &seeds);
+
     bool is_const(uint32_t n) const { return nodes_[n].op == CONST; }
     bool is_const(uint32_t n, double v) const {
         return nodes_[n].op == CONST && nodes_[n].val == v;

@@ -132,14 +132,18 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
 
     // ---- emit the VJP
     if (p->has_vjp) {
-        uint32_t s = g.constant(0.0);
-        for (uint32_t j = 0; j < ny; j++) s = g.add(s, g.mul(g.var(VK_SEED, j), f[j]));
+        // reverse mode: adjoints of s = sum_j v_j f_j with respect to the
+        // state, the parameter elements and the spline nodes
+        std::vector<uint32_t> seeds(ny);
+        for (uint32_t j = 0; j < ny; j++) seeds[j] = g.var(VK_SEED, j);
+        const std::vector<uint32_t> adj = g.adjoints(f, seeds);
+        auto A = [&](uint32_t n) { return adj[n] == NONE ? g.constant(0.0) : adj[n]; };
         FunctionSpec spec;
         spec.signature =
             "RG_FN void rg_vjp(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, const double *__restrict__ av, double *__restrict__ jv, "
             "double *__restrict__ gp, rg_GA &G) {\n  (void)om; (void)t; (void)P; (void)gp; (void)G;";
-        for (uint32_t j = 0; j < ny; j++) spec.outputs.push_back({g.df(s, yv[j]), "jv[" + std::to_string(j) + "]", false});
+        for (uint32_t j = 0; j < ny; j++) spec.outputs.push_back({A(yv[j]), "jv[" + std::to_string(j) + "]", false});
         std::vector<uint32_t> freach = g.reachable(f);
         for (uint32_t n : freach) {
             const Node &nd = g.node(n);
@@ -147,12 +151,12 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
                 int slot = (int)p->grad_param.size();
                 p->grad_param.push_back(nd.aux);
                 p->grad_elem.push_back((int)nd.val);
-                spec.outputs.push_back({g.df(s, n), "gp[" + std::to_string(slot) + "]", true});
+                spec.outputs.push_back({A(n), "gp[" + std::to_string(slot) + "]", true});
             }
         }
         for (uint32_t n : freach) {
             const Node &nd = g.node(n);
-            if (nd.op == SPLINE) spec.spline_seeds.push_back({n, g.df(s, n)});
+            if (nd.op == SPLINE) spec.spline_seeds.push_back({n, A(n)});
         }
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;

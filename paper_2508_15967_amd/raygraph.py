@@ -232,7 +232,8 @@ class Graph:
         self.param_names: List[str] = []
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # module globals may already be cleared at interpreter exit
+        if getattr(self, "h", None) and _lib is not None:
             _lib.rg_destroy_graph(self.h)
             self.h = None
 
@@ -350,7 +351,8 @@ class Program:
         self.param_names = param_names
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # module globals may already be cleared at interpreter exit
+        if getattr(self, "h", None) and _lib is not None:
             _lib.rg_destroy_program(self.h)
             self.h = None
 
