@@ -102,12 +102,33 @@ __device__ __forceinline__ bool rg_outside(const rg_kargs &a, const double *y) {
 // Components whose right-hand side is identically zero (RG_RHS_ZERO, known
 // when the graph is compiled) keep their value through every stage: the
 // stage arithmetic would add exact zeros to them.
+//
+// With RG_ROLL (a right-hand side with many distinct constants) the four
+// stages are a loop around one copy of the right-hand side: the constants,
+// which live in scalar registers, are then live for one stage only instead
+// of across four inlined copies (which overflows the scalar register file
+// into vector-register lanes).  The arithmetic is the same in both forms.
 #define RG_ZERO(i) ((RG_RHS_ZERO >> (i)) & 1u)
 
 __device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t, double dt,
                                             const rg_P &P, double *yn) {
     const double h2 = 0.5 * dt, dt6 = dt / 6.0;
     double K[RG_NY], acc[RG_NY], Y[RG_NY];
+#if RG_ROLL
+    const double th = t + h2, tf = t + dt;
+    for (int i = 0; i < RG_NY; i++) Y[i] = y[i];
+#pragma unroll 1
+    for (int s = 0; s < 4; s++) {
+        rg_rhs(Y, om, s == 0 ? t : (s == 3 ? tf : th), P, K);
+        if (s == 3) break;
+        const double c = s == 2 ? dt : h2;
+        for (int i = 0; i < RG_NY; i++)
+            if (!RG_ZERO(i)) {
+                acc[i] = s == 0 ? K[i] : fma(2.0, K[i], acc[i]);
+                Y[i] = fma(c, K[i], y[i]);
+            }
+    }
+#else
     rg_rhs(y, om, t, P, K);
     for (int i = 0; i < RG_NY; i++) { acc[i] = K[i]; Y[i] = RG_ZERO(i) ? y[i] : fma(h2, K[i], y[i]); }
     rg_rhs(Y, om, t + h2, P, K);
@@ -119,6 +140,7 @@ __device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t
         if (!RG_ZERO(i)) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
     }
     rg_rhs(Y, om, t + dt, P, K);
+#endif
     for (int i = 0; i < RG_NY; i++) yn[i] = RG_ZERO(i) ? y[i] : fma(dt6, acc[i] + K[i], y[i]);
 }
 
@@ -609,7 +631,48 @@ __shared__ double rg_red_lds[8 * RG_NGRAD1];
 // Segments between forward checkpoints are walked last to first; the states
 // of a segment are recomputed from its checkpoint into per-lane scratch
 // (coalesced [j][c][lane]) and read back in reverse.
-extern "C" __global__ void __launch_bounds__(512) rg_rk4_adjoint(rg_kargs a) {
+#if RG_ROLL
+// Reverse of one RK4 step with one copy of the right-hand side and one of
+// the VJP (see RG_ROLL above): the stage states Y2..Y4 wait in LDS (one
+// slot per lane and component), Y1 is re-read from the segment buffer.
+// Same arithmetic as the unrolled form.
+__shared__ double rg_stage_lds[3 * RG_NY * RG_ADJ_BLOCK];
+
+__device__ __forceinline__ void rg_adjoint_step_rolled(const double *sp, long long SL, double om,
+                                                       double dt, const rg_P &P, double *lam,
+                                                       double *gp, rg_GA &G) {
+    const double h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
+    const int tid = threadIdx.x;
+    const double tj = sp[(long long)RG_NY * SL];
+    double Y[RG_NY], K[RG_NY];
+    for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)c * SL];
+#pragma unroll 1
+    for (int s = 0; s < 3; s++) {
+        rg_rhs(Y, om, s == 0 ? tj : tj + h2, P, K);
+        const double cs = s == 2 ? dt : h2;
+        for (int c = 0; c < RG_NY; c++) {
+            Y[c] = fma(cs, K[c], sp[(long long)c * SL]);
+            rg_stage_lds[(s * RG_NY + c) * RG_ADJ_BLOCK + tid] = Y[c];
+        }
+    }
+    double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY];
+    for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
+#pragma unroll 1
+    for (int s = 3; s >= 0; s--) {
+        for (int c = 0; c < RG_NY; c++)
+            Y[c] = s == 0 ? sp[(long long)c * SL] : rg_stage_lds[((s - 1) * RG_NY + c) * RG_ADJ_BLOCK + tid];
+        rg_vjp(Y, om, s == 0 ? tj : (s == 3 ? tj + dt : tj + h2), P, Kb, Yb, gp, G);
+        const double ca = s == 3 ? dt : h2, cb = s == 1 ? dt6 : dt3;
+        for (int c = 0; c < RG_NY; c++) {
+            lsum[c] = s == 3 ? Yb[c] : lsum[c] + Yb[c];
+            Kb[c] = fma(ca, Yb[c], cb * lam[c]);
+        }
+    }
+    for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + lsum[c];
+}
+#endif
+
+extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kargs a) {
     rg_stage_tables(a);
 #if RG_NSPLTAB > 0
     for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) rg_spl_grad_lds[i] = 0.0;
@@ -654,6 +717,9 @@ extern "C" __global__ void __launch_bounds__(512) rg_rk4_adjoint(rg_kargs a) {
             }
             for (int j = s1 - 1; j >= s0; j--) {
                 const double *sp = a.scratch + (long long)(j - s0) * (RG_NY + 1) * SL + gid;
+#if RG_ROLL
+                rg_adjoint_step_rolled(sp, SL, om, dt, P, lam, gp, G);
+#else
                 double Y1[RG_NY], Y2[RG_NY], Y3[RG_NY], Y4[RG_NY], K[RG_NY];
                 for (int c = 0; c < RG_NY; c++) Y1[c] = sp[(long long)c * SL];
                 const double tj = sp[(long long)RG_NY * SL];
@@ -673,6 +739,7 @@ extern "C" __global__ void __launch_bounds__(512) rg_rk4_adjoint(rg_kargs a) {
                 for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt6 * lam[c]); }
                 rg_vjp(Y1, om, tj, P, Kb, Yb, gp, G);
                 for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + (lsum[c] + Yb[c]);
+#endif
             }
         }
         for (int i = 0; i < RG_DIM; i++) {

@@ -10,6 +10,8 @@
 // vector-Jacobian products J^T v and (df/dtheta)^T v.
 #include <hip/hiprtc.h>
 
+#include <cmath>
+
 #include <chrono>
 #include <cstring>
 #include <sstream>
@@ -74,6 +76,17 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     unsigned zero_mask = 0;  // components whose right-hand side is identically 0
     for (uint32_t i = 0; i < ny; i++)
         if (g.is_const(f[i], 0.0)) zero_mask |= 1u << i;
+    // distinct constants of the right-hand side that are not inline operands
+    // of FP64 instructions (0, +-0.5, +-1, +-2, +-4); each takes two scalar
+    // registers where it is used
+    uint32_t n_consts = 0;
+    for (uint32_t n : g.reachable(f)) {
+        const Node &nd = g.node(n);
+        if (nd.op != CONST) continue;
+        const double v = std::fabs(nd.val);
+        if (v == 0.0 || v == 0.5 || v == 1.0 || v == 2.0 || v == 4.0) continue;
+        n_consts++;
+    }
 
     // ---- spline tables used by the program
     std::vector<uint32_t> roots(f.begin(), f.end());
@@ -95,6 +108,11 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     }
     if (p->spl_total > 8192)
         return fail(RG_EUNSUPPORTED, "spline tables larger than 8192 coefficients (LDS staging)");
+    // Rolled stage loops (one copy of the right-hand side per kernel loop)
+    // for right-hand sides with many constants; they also stage the adjoint's
+    // stage states in LDS (3 * 2*dim doubles per lane), next to the spline
+    // tables and their gradient accumulator.
+    p->rolled = n_consts > 32 && p->spl_total <= 4096;
 
     // ---- emit rhs and D
     std::ostringstream fs;
@@ -169,7 +187,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
        << p->n_params << "\n#define RG_NGRAD " << p->grad_param.size() << "\n#define RG_NSPLTAB "
        << p->spl_param.size() << "\n#define RG_SPL_TOTAL " << (p->spl_total ? p->spl_total : 1)
        << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_RHS_ZERO " << zero_mask
-       << "u\n";
+       << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_BLOCK " << kAdjointBlock
+       << "\n";
     cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)
        << int_array("rg_spl_len", p->spl_len) << int_array("rg_spl_ny", p->spl_ny)
        << int_array("rg_grad_param", p->grad_param) << int_array("rg_grad_elem", p->grad_elem);
@@ -236,9 +255,13 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         HIPRTC_SUCCESS)
         return fail(RG_ECOMPILE, "hiprtcCreateProgram failed");
     // no FP contraction beyond the fma written in the source; no packed FP32
+    // With rolled stage loops, machine-level loop-invariant code motion is
+    // off: it would hoist every constant's scalar-register materialization
+    // out of the stage loop and so keep them all live again.
     const char *copts[] = {arch_opt.c_str(), o_opt.c_str(), "-ffp-contract=off", "-std=c++17",
-                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    hiprtcResult rc = hiprtcCompileProgram(prog, 8, copts);
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "-mllvm", "-disable-machine-licm"};
+    hiprtcResult rc = hiprtcCompileProgram(prog, p->rolled ? 10 : 8, copts);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);

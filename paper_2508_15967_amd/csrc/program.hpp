@@ -14,6 +14,10 @@
 #include "graph.hpp"
 #include "kernels/rg_kargs.h"
 
+// Largest workgroup of the adjoint kernel (its launch bound and the size of
+// its per-lane LDS staging).
+constexpr int kAdjointBlock = 256;
+
 struct TuneEntry {
     int block = 256, rpl = 1, compact = 64;
 };
@@ -30,6 +34,7 @@ struct rg_program {
     std::vector<uint32_t> param_len;
     bool has_vjp = false;
     bool compile_only = false;
+    bool rolled = false;  // RK4 stage loops rolled (RG_ROLL)
     // gradient layout
     std::vector<int> grad_param, grad_elem;       // scalar slots
     std::vector<int> spl_param, spl_off, spl_len, spl_ny;

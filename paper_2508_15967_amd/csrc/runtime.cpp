@@ -559,7 +559,7 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     a.gx0 = ad.dL_dx0;
     a.gk0 = ad.dL_dk0;
 
-    const int block = d.block ? d.block : 256;
+    const int block = d.block > 0 && d.block < kAdjointBlock ? d.block : kAdjointBlock;
     unsigned grid;
     RGCHK(occupancy_grid(p, "rg_rk4_adjoint", block, (long long)cdiv(n, block), &grid));
     const long long lanes = (long long)grid * block;
