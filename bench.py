@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the single precision side measurement (RK4 forward workloads)")
     return ap.parse_args()
 
 
@@ -234,6 +236,32 @@ def main():
                           "fwd_adj_ray_steps_per_s": ray_steps / ((hf + hb) * 1e-3),
                           "compiled_over_hand_fwd": hf / fwd_ms,
                           "compiled_over_hand_fwd_adj": (hf + hb) / (fwd_ms + bwd_ms)}
+
+    # single precision variant (float state and right-hand side, same outputs
+    # in double, D residual monitored in double): a side line, not the metric
+    if not args.no_fp32 and w.integrator == W.RK4 and not adjoint and w.medium.kind != W.SPLINE2D:
+        prog32 = g.compile(D, fp32=True)
+        x64, k64 = outs["x_out"].clone(), outs["k_out"].clone()
+        desc32 = prog32.make_desc(x0, k0, om, pt, mode=rgb.PERSISTENT, use_hipgraph=True,
+                                  precision=rgb.FP32, block=args.block, **kw, **outs)
+        prog32.trace_desc(desc32, stream)  # warm: tuning and capture
+        torch.cuda.synchronize()
+        e32 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a_, b_ in e32:
+            a_.record(stream)
+            prog32.trace_desc(desc32, stream)
+            b_.record(stream)
+        torch.cuda.synchronize()
+        ms32 = float(np.mean([a_.elapsed_time(b_) for a_, b_ in e32]))
+        steps32 = int(outs["steps_out"].cpu().numpy().astype(np.int64).sum())
+        dx = torch.linalg.vector_norm(outs["x_out"] - x64, dim=0) / torch.clamp(
+            torch.linalg.vector_norm(x64, dim=0), min=1.0)
+        result["fp32"] = {"value": steps32 / (ms32 * 1e-3), "unit": "ray-steps/s", "ms_per_trace": ms32,
+                          "speedup_vs_fp64": fwd_ms / ms32, "launch": prog32.last_launch(),
+                          "max_rel_dev_x_vs_fp64": float(dx.max())}
+        outs["x_out"].copy_(x64)
+        outs["k_out"].copy_(k64)
 
     # plain one-launch-per-step comparator on the same GPU and inputs
     if not args.no_plain:

@@ -79,6 +79,7 @@ enum {
 };
 enum { RG_RK4 = 0, RG_DOPRI54 = 1 };
 enum { RG_PERSISTENT = 0, RG_PLAIN = 1 };
+enum { RG_FP64 = 0, RG_FP32 = 1 };
 /* Per-ray termination status. */
 enum {
     RG_RAY_OK = 0,            /* ran all steps (RK4) or reached t_end */
@@ -157,6 +158,9 @@ typedef struct {
                                (works without a GPU) */
     int32_t opt_level;      /* hipRTC -O level, 0 = default (3) */
     const char *arch;       /* NULL = "gfx950" */
+    int32_t fp32;           /* 1: also emit a single precision right-hand side and
+                               build the RG_FP32 persistent RK4 kernel (graphs
+                               without spline nodes; RG_EUNSUPPORTED otherwise) */
 } rg_compile_opts;
 
 /* Differentiate D (eqs. 2-3), reduce and CSE, emit the HIP right-hand side
@@ -233,6 +237,11 @@ typedef struct {
     int32_t compact_interval;   /* DOPRI54: refill dead lanes every this many attempts,
                                    0 = tuned, -1 = only when a whole wave is dead */
     int32_t *attempts_out;      /* DOPRI54: [n] step attempts incl. rejected ones, nullable */
+    int32_t precision;          /* RG_FP64, or RG_FP32: state, stages and right-hand
+                                   side in single precision (RK4, RG_PERSISTENT, no
+                                   checkpoints, program compiled with fp32 = 1); the
+                                   arrays stay double, t and the traj_D residual
+                                   are computed in double */
 } rg_trace_desc;
 
 /* Trace n_rays rays.  RK4 runs exactly n_steps steps per ray (fewer if it
@@ -256,11 +265,12 @@ typedef struct {
 /* Discrete adjoint of the RK4 trajectory (exact transpose of the step map),
  * reverse sweep segment by segment from the forward checkpoints with the
  * states of each segment recomputed.  Gradients of a loss L whose
- * derivatives at the endpoints are given. */
+ * derivatives at the endpoints are given.  Workgroups hold
+ * min(fwd->block, 256) threads (256 when fwd->block is 0). */
 rg_status rg_trace_rays_adjoint(rg_program *p, const rg_adjoint_desc *d, void *hip_stream);
 
-/* Elementwise evaluation of D and the right-hand side at n points (the
- * paper's Listing-1 style work item: inputs -> outputs, no time stepping).
+/* Elementwise evaluation of D and the right-hand side at n points (one
+ * independent work item per point: inputs -> outputs, no time stepping).
  * y: [2*dim][n], omega: [n], f_out: [2*dim][n] (nullable), D_out: [n]
  * (nullable).  Device pointers. */
 rg_status rg_eval_rays(rg_program *p, uint32_t n, const double *y, const double *omega,

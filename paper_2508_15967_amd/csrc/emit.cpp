@@ -37,6 +37,16 @@ std::string hex_double(double v) {
     return buf;
 }
 
+// A float literal holding v rounded to single precision.
+static std::string hex_float(double v) {
+    const float f = (float)v;
+    char buf[64];
+    if (std::isnan(f)) return "(__builtin_nanf(\"\"))";
+    if (std::isinf(f)) return f > 0 ? "(__builtin_inff())" : "(-__builtin_inff())";
+    std::snprintf(buf, sizeof buf, "(%af)", (double)f);
+    return buf;
+}
+
 namespace {
 
 struct Emitter {
@@ -66,6 +76,11 @@ struct Emitter {
     std::vector<int> chain_of_root;  // node -> chain index or -1
     std::vector<char> interior;      // node folded into a chain
     std::vector<uint32_t> consumer;  // unique consumer of a single-use node
+    bool f32 = false;                // emit single precision (float) code
+
+    const char *T() const { return f32 ? "float" : "double"; }
+    std::string lit(double v) const { return f32 ? hex_float(v) : hex_double(v); }
+    std::string fn(const char *base) const { return f32 ? std::string(base) + "f" : std::string(base); }
 
     Emitter(const Graph &g_, const std::vector<int> &ts) : g(g_), table_slot(ts) {
         uses.assign(g.size(), 0);
@@ -78,7 +93,7 @@ struct Emitter {
 
     std::string name(uint32_t n) const {
         const Node &nd = g.node(n);
-        if (nd.op == CONST) return hex_double(nd.val);
+        if (nd.op == CONST) return lit(nd.val);
         if (nd.op == VAR) {
             int kind = nd.aux / 8, i = nd.aux % 8;
             uint32_t d = g.dim();
@@ -240,7 +255,8 @@ struct Emitter {
         case CONST: case VAR:
             return;
         case PARAM:
-            os << "  const double " << name(n) << " = P.p[" << nd.aux << "][" << (size_t)nd.val << "];\n";
+            os << "  const " << T() << " " << name(n) << " = " << (f32 ? "(float)" : "") << "P.p[" << nd.aux
+               << "][" << (size_t)nd.val << "];\n";
             return;
         case SPLINE: {
             int gi = group_of.at(n);
@@ -263,11 +279,11 @@ struct Emitter {
             bool fb = !fa && fused[nd.b] && g.node(nd.b).op == MUL;
             if (fa) {
                 const Node &m = g.node(nd.a);
-                e = "fma(" + name(m.a) + ", " + name(m.b) + ", " + (nd.op == SUB ? "-" : "") + B + ")";
+                e = fn("fma") + "(" + name(m.a) + ", " + name(m.b) + ", " + (nd.op == SUB ? "-" : "") + B + ")";
                 count_fma();
             } else if (fb) {
                 const Node &m = g.node(nd.b);
-                e = "fma(" + std::string(nd.op == SUB ? "-" : "") + name(m.a) + ", " + name(m.b) + ", " + A + ")";
+                e = fn("fma") + "(" + std::string(nd.op == SUB ? "-" : "") + name(m.a) + ", " + name(m.b) + ", " + A + ")";
                 count_fma();
             } else {
                 e = A + (nd.op == ADD ? " + " : " - ") + B;
@@ -278,7 +294,7 @@ struct Emitter {
         case MUL: e = A + " * " + B; count(MUL); break;
         case DIV:
             if (g.is_const(nd.a, 1.0)) {
-                e = "rg_rcp(" + B + ")";
+                e = fn("rg_rcp") + "(" + B + ")";
                 fl.alg += 1; fl.issued += issued_weights().rcp; fl.ops++;
             } else {
                 e = A + " / " + B;
@@ -286,23 +302,23 @@ struct Emitter {
             }
             break;
         case NEG: e = "-" + A; break;
-        case EXP: e = "exp(" + A + ")"; count(EXP); break;
-        case LOG: e = "log(" + A + ")"; count(LOG); break;
-        case SQRT: e = "sqrt(" + A + ")"; count(SQRT); break;
-        case SIN: e = "sin(" + A + ")"; count(SIN); break;
-        case COS: e = "cos(" + A + ")"; count(COS); break;
+        case EXP: e = fn("exp") + "(" + A + ")"; count(EXP); break;
+        case LOG: e = fn("log") + "(" + A + ")"; count(LOG); break;
+        case SQRT: e = fn("sqrt") + "(" + A + ")"; count(SQRT); break;
+        case SIN: e = fn("sin") + "(" + A + ")"; count(SIN); break;
+        case COS: e = fn("cos") + "(" + A + ")"; count(COS); break;
         case POWI: {
             int k = nd.aux < 0 ? -nd.aux : nd.aux;
             std::string p = A;
             for (int i = 1; i < k; i++) p += " * " + A;
-            e = nd.aux < 0 ? "1.0 / (" + p + ")" : p;
+            e = nd.aux < 0 ? lit(1.0) + " / (" + p + ")" : p;
             count(POWI, nd.aux);
             break;
         }
         default:
             throw std::logic_error("emit: unexpected node");
         }
-        os << "  const double " << name(n) << " = " << e << ";\n";
+        os << "  const " << T() << " " << name(n) << " = " << e << ";\n";
     }
 
     // One term of a chain: the first defines the accumulator, the others
@@ -323,12 +339,12 @@ struct Emitter {
             } else {
                 t = std::string(sg < 0 ? "-" : "") + name(leaf);
             }
-            os << "  double " << R << " = " << t << ";\n";
+            os << "  " << T() << " " << R << " = " << t << ";\n";
             return;
         }
         if (prod) {
             const Node &m = g.node(leaf);
-            os << "  " << R << " = fma(" << (sg < 0 ? "-" : "") << name(m.a) << ", " << name(m.b) << ", " << R
+            os << "  " << R << " = " << fn("fma") << "(" << (sg < 0 ? "-" : "") << name(m.a) << ", " << name(m.b) << ", " << R
                << ");\n";
             count_fma();
         } else {
@@ -633,6 +649,8 @@ struct Emitter {
 std::string emit_function(const Graph &g, const FunctionSpec &spec,
                           const std::vector<int> &param_table_slot, Flops *flops) {
     Emitter em(g, param_table_slot);
+    em.f32 = spec.fp32;
+    if (spec.fp32 && !spec.spline_seeds.empty()) throw std::invalid_argument("single precision VJP");
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);
     for (const SplineSeed &s : spec.spline_seeds) {

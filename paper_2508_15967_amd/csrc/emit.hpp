@@ -50,6 +50,7 @@ struct FunctionSpec {
     std::vector<Output> outputs;
     std::vector<SplineSeed> spline_seeds;  // VJP only
     bool returns_value = false;            // single output via "return"
+    bool fp32 = false;                     // single precision (no spline nodes)
 };
 
 // Emit a function.  `tables` maps a spline-definition's parameter to a table

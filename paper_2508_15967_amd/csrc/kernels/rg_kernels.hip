@@ -85,15 +85,19 @@ __device__ __forceinline__ rg_P rg_params(const rg_kargs &a) {
     return P;
 }
 
-__device__ __forceinline__ bool rg_finite(const double *y) {
+template <typename T>
+__device__ __forceinline__ bool rg_finite(const T *y) {
     bool f = true;
     for (int i = 0; i < RG_NY; i++) f = f && __builtin_isfinite(y[i]);
     return f;
 }
 
-__device__ __forceinline__ bool rg_outside(const rg_kargs &a, const double *y) {
+// strictly outside the box (a single precision state is compared exactly,
+// promoted to double)
+template <typename T>
+__device__ __forceinline__ bool rg_outside(const rg_kargs &a, const T *y) {
     bool o = false;
-    for (int i = 0; i < RG_DIM; i++) o = o || (y[i] < a.box_lo[i]) || (y[i] > a.box_hi[i]);
+    for (int i = 0; i < RG_DIM; i++) o = o || ((double)y[i] < a.box_lo[i]) || ((double)y[i] > a.box_hi[i]);
     return o;
 }
 
@@ -110,21 +114,21 @@ __device__ __forceinline__ bool rg_outside(const rg_kargs &a, const double *y) {
 // into vector-register lanes).  The arithmetic is the same in both forms.
 #define RG_ZERO(i) ((RG_RHS_ZERO >> (i)) & 1u)
 
-__device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t, double dt,
-                                            const rg_P &P, double *yn) {
-    const double h2 = 0.5 * dt, dt6 = dt / 6.0;
-    double K[RG_NY], acc[RG_NY], Y[RG_NY];
+template <typename T>
+__device__ __forceinline__ void rg_rk4_step(const T *y, T om, T t, T dt, const rg_P &P, T *yn) {
+    const T h2 = T(0.5) * dt, dt6 = dt / T(6.0);
+    T K[RG_NY], acc[RG_NY], Y[RG_NY];
 #if RG_ROLL
-    const double th = t + h2, tf = t + dt;
+    const T th = t + h2, tf = t + dt;
     for (int i = 0; i < RG_NY; i++) Y[i] = y[i];
 #pragma unroll 1
     for (int s = 0; s < 4; s++) {
         rg_rhs(Y, om, s == 0 ? t : (s == 3 ? tf : th), P, K);
         if (s == 3) break;
-        const double c = s == 2 ? dt : h2;
+        const T c = s == 2 ? dt : h2;
         for (int i = 0; i < RG_NY; i++)
             if (!RG_ZERO(i)) {
-                acc[i] = s == 0 ? K[i] : fma(2.0, K[i], acc[i]);
+                acc[i] = s == 0 ? K[i] : fma(T(2.0), K[i], acc[i]);
                 Y[i] = fma(c, K[i], y[i]);
             }
     }
@@ -133,11 +137,11 @@ __device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t
     for (int i = 0; i < RG_NY; i++) { acc[i] = K[i]; Y[i] = RG_ZERO(i) ? y[i] : fma(h2, K[i], y[i]); }
     rg_rhs(Y, om, t + h2, P, K);
     for (int i = 0; i < RG_NY; i++) {
-        if (!RG_ZERO(i)) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(h2, K[i], y[i]); }
+        if (!RG_ZERO(i)) { acc[i] = fma(T(2.0), K[i], acc[i]); Y[i] = fma(h2, K[i], y[i]); }
     }
     rg_rhs(Y, om, t + h2, P, K);
     for (int i = 0; i < RG_NY; i++) {
-        if (!RG_ZERO(i)) { acc[i] = fma(2.0, K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
+        if (!RG_ZERO(i)) { acc[i] = fma(T(2.0), K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
     }
     rg_rhs(Y, om, t + dt, P, K);
 #endif
@@ -146,29 +150,41 @@ __device__ __forceinline__ void rg_rk4_step(const double *y, double om, double t
 
 // ------------------------------------------------------- persistent RK4 --
 // Grid-stride over rays; R rays per lane advanced in lock-step so that the
-// compiler can interleave their independent right-hand sides.
-template <int R>
+// compiler can interleave their independent right-hand sides.  T is the
+// arithmetic type of the state and the stages (double, or float for the
+// single precision variant, whose inputs and outputs stay double and whose
+// time and D-residual snapshots are computed in double).
+template <typename T>
+__device__ __forceinline__ double rg_D_mon(const T *y, double om, double t, const rg_P &P) {
+    double yd[RG_NY];
+    for (int c = 0; c < RG_NY; c++) yd[c] = (double)y[c];
+    return rg_D(yd, om, t, P);
+}
+
+template <typename T, int R>
 __device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
     rg_stage_tables(a);
     const rg_P P = rg_params(a);
     const long long n = a.n;
     const long long G = (long long)gridDim.x * blockDim.x;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const double dt = a.dt;
+    const double dtd = a.dt;
+    const T dt = (T)dtd;
     const long long nr = a.n_run;
     for (long long base = gid; base < nr; base += G * R) {
-        double y[R][RG_NY], t[R], om[R];
+        T y[R][RG_NY], om[R];
+        double t[R];
         int st[R], ns[R];
         long long rid[R];
         for (int r = 0; r < R; r++) {
             rid[r] = base + (long long)r * G;
             const long long q = rid[r] < nr ? rid[r] : base;  // inactive slot re-reads a valid ray
             for (int i = 0; i < RG_DIM; i++) {
-                y[r][i] = a.x0[i * n + q];
-                y[r][RG_DIM + i] = a.k0[i * n + q];
+                y[r][i] = (T)a.x0[i * n + q];
+                y[r][RG_DIM + i] = (T)a.k0[i * n + q];
             }
             t[r] = a.t0 ? a.t0[q] : 0.0;
-            om[r] = a.omega[q];
+            om[r] = (T)a.omega[q];
             st[r] = rid[r] < nr ? RG_RAY_OK : -1;
             ns[r] = 0;
         }
@@ -177,7 +193,7 @@ __device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
             for (int r = 0; r < R; r++)
                 if (st[r] >= 0) {
                     for (int c = 0; c < RG_NY; c++) a.traj[(long long)c * n + rid[r]] = y[r][c];
-                    if (a.traj_D) a.traj_D[rid[r]] = rg_D(y[r], om[r], t[r], P);
+                    if (a.traj_D) a.traj_D[rid[r]] = rg_D_mon(y[r], a.omega[rid[r]], t[r], P);
                 }
             snap = 1;
         }
@@ -193,14 +209,14 @@ __device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
                 ck_cd = a.ckpt_every;
             }
             ck_cd--;
-            double yn[R][RG_NY];
-            for (int r = 0; r < R; r++) rg_rk4_step(y[r], om[r], t[r], dt, P, yn[r]);
+            T yn[R][RG_NY];
+            for (int r = 0; r < R; r++) rg_rk4_step(y[r], om[r], (T)t[r], dt, P, yn[r]);
             for (int r = 0; r < R; r++) {
                 const bool fin = rg_finite(yn[r]);
                 const bool live = st[r] == RG_RAY_OK;
                 if (live && fin) {
                     for (int c = 0; c < RG_NY; c++) y[r][c] = yn[r][c];
-                    t[r] = t[r] + dt;
+                    t[r] = t[r] + dtd;
                     ns[r]++;
                     if (a.has_box && rg_outside(a, y[r])) st[r] = RG_RAY_EXITED_BOX;
                 } else if (live) {
@@ -212,7 +228,8 @@ __device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
                     if (st[r] >= 0) {
                         double *tp = a.traj + (long long)snap * RG_NY * n + rid[r];
                         for (int c = 0; c < RG_NY; c++) tp[(long long)c * n] = y[r][c];
-                        if (a.traj_D) a.traj_D[(long long)snap * n + rid[r]] = rg_D(y[r], om[r], t[r], P);
+                        if (a.traj_D)
+                            a.traj_D[(long long)snap * n + rid[r]] = rg_D_mon(y[r], a.omega[rid[r]], t[r], P);
                     }
                 snap++;
                 snap_cd = a.store_every;
@@ -231,8 +248,11 @@ __device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
     }
 }
 
-extern "C" __global__ void __launch_bounds__(512) rg_rk4_r1(rg_kargs a) { rg_rk4_persistent<1>(a); }
-extern "C" __global__ void __launch_bounds__(512) rg_rk4_r2(rg_kargs a) { rg_rk4_persistent<2>(a); }
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_r1(rg_kargs a) { rg_rk4_persistent<double, 1>(a); }
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_r2(rg_kargs a) { rg_rk4_persistent<double, 2>(a); }
+#if RG_HAS_F32
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_f32(rg_kargs a) { rg_rk4_persistent<float, 1>(a); }
+#endif
 
 // ------------------------------------------------------------ plain RK4 --
 // One step per launch: load state, one step, store state (the paper's

@@ -30,6 +30,18 @@ RG_FN double rg_rcp(double d) {
 #endif
 }
 
+// Single precision reciprocal: the hardware estimate and one Newton step
+// (about one ulp of 1/d for normal finite d).
+RG_FN float rg_rcpf(float d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    float r = __builtin_amdgcn_rcpf(d);
+    const float e = fmaf(-d, r, 1.0f);
+    return fmaf(e, r, r);
+#else
+    return 1.0f / d;
+#endif
+}
+
 // Cell of a uniform cubic B-spline with n coefficients: s = (x - lo)/h + 1,
 // m = clamp(floor(s), 1, n - 3), u = s - m (u leaves [0,1] outside the
 // domain, extending the edge cell's cubic).  4 flops.

@@ -125,6 +125,21 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         fs << emit_function(g, spec, table_slot, &fl_rhs);
     }
+    if (opts.fp32) {
+        // the same right-hand side in single precision (an overload of rg_rhs)
+        for (uint32_t n : g.reachable(f))
+            if (g.node(n).op == SPLINE)
+                return fail(RG_EUNSUPPORTED, "single precision right-hand side with spline nodes");
+        FunctionSpec spec;
+        spec.fp32 = true;
+        spec.signature =
+            "RG_FN void rg_rhs(const float *__restrict__ y, const float om, const float t, "
+            "const rg_P &P, float *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
+        for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
+        Flops fl32;
+        fs << emit_function(g, spec, table_slot, &fl32);
+        p->has_f32 = true;
+    }
     {
         FunctionSpec spec;
         spec.signature =
@@ -186,7 +201,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     cs << "#pragma once\n#define RG_DIM " << d << "\n#define RG_NY " << ny << "\n#define RG_NPARAM "
        << p->n_params << "\n#define RG_NGRAD " << p->grad_param.size() << "\n#define RG_NSPLTAB "
        << p->spl_param.size() << "\n#define RG_SPL_TOTAL " << (p->spl_total ? p->spl_total : 1)
-       << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_RHS_ZERO " << zero_mask
+       << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_HAS_F32 " << (p->has_f32 ? 1 : 0)
+       << "\n#define RG_RHS_ZERO " << zero_mask
        << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_BLOCK " << kAdjointBlock
        << "\n";
     cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)

@@ -31,7 +31,7 @@ namespace rg {
 static const char *const KERNELS[] = {
     "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
     "rg_dopri_persistent", "rg_dopri_plain_init", "rg_dopri_plain_step", "rg_fill_f64",
-    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k"};
+    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k", "rg_rk4_f32"};
 
 static void drop_graphs(rg_program *p) {
     for (GraphEntry &ge : p->graphs) {
@@ -231,6 +231,14 @@ static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
     if (d.block != 0 && d.block != 64 && d.block != 128 && d.block != 256 && d.block != 512)
         return fail(RG_EINVAL, "block must be 0, 64, 128, 256 or 512");
     if (d.rays_per_lane < 0 || d.rays_per_lane > 2) return fail(RG_EINVAL, "rays_per_lane must be 0, 1 or 2");
+    if (d.precision != RG_FP64 && d.precision != RG_FP32) return fail(RG_EINVAL, "unknown precision");
+    if (d.precision == RG_FP32) {
+        if (!p->has_f32) return fail(RG_ESTATE, "RG_FP32 needs a program compiled with fp32 = 1");
+        if (d.integrator != RG_RK4 || d.mode != RG_PERSISTENT)
+            return fail(RG_EUNSUPPORTED, "RG_FP32 is implemented for persistent RK4");
+        if (d.checkpoint_every != 0) return fail(RG_EUNSUPPORTED, "RG_FP32 traces keep no adjoint checkpoints");
+        if (d.rays_per_lane > 1) return fail(RG_EUNSUPPORTED, "RG_FP32 runs one ray per lane");
+    }
     std::memset(&a, 0, sizeof a);
     a.n = (long long)n;
     a.n_run = (long long)n;
@@ -335,8 +343,8 @@ static std::string tune_key(rg_program *p, const char *what, long long n) {
 }
 
 static rg_status persistent_rk4_seq(rg_program *p, const rg_kargs &a, int block, int rpl,
-                                    std::vector<Launch> &seq) {
-    const char *name = rpl == 2 ? "rg_rk4_r2" : "rg_rk4_r1";
+                                    std::vector<Launch> &seq, bool fp32 = false) {
+    const char *name = fp32 ? "rg_rk4_f32" : rpl == 2 ? "rg_rk4_r2" : "rg_rk4_r1";
     unsigned grid;
     RGCHK(occupancy_grid(p, name, block, (long long)cdiv(a.n_run, (long long)block * rpl), &grid));
     seq.push_back(Launch{name, grid, (unsigned)block, a});
@@ -361,8 +369,8 @@ static rg_status dopri_seq(rg_program *p, rg_kargs a, int block, int compact, st
     return RG_OK;
 }
 
-static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneEntry *out) {
-    std::string key = tune_key(p, "rk4", a.n);
+static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneEntry *out, bool fp32) {
+    std::string key = tune_key(p, fp32 ? "rk4f32" : "rk4", a.n);
     if (p->tune.empty()) tune_load(p);
     auto it = p->tune.find(key);
     if (it != p->tune.end()) { *out = it->second; p->last.tuned = 1; return RG_OK; }
@@ -377,8 +385,9 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     TuneEntry bt;
     for (int rpl : {1, 2})
         for (int block : {64, 128, 256, 512}) {
+            if (fp32 && rpl > 1) continue;
             std::vector<Launch> seq;
-            RGCHK(persistent_rk4_seq(p, t, block, rpl, seq));
+            RGCHK(persistent_rk4_seq(p, t, block, rpl, seq, fp32));
             float ms;
             RGCHK(time_seq(p, seq, s, &ms));
             if (ms < best) { best = ms; bt.block = block; bt.rpl = rpl; }
@@ -429,12 +438,13 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
     const bool graph = d.use_hipgraph != 0;
 
     if (d.integrator == RG_RK4 && d.mode == RG_PERSISTENT) {
+        const bool fp32 = d.precision == RG_FP32;
         TuneEntry te;
-        if (d.block == 0 || d.rays_per_lane == 0) RGCHK(tune_rk4(p, a, s, &te));
+        if (d.block == 0 || (d.rays_per_lane == 0 && !fp32)) RGCHK(tune_rk4(p, a, s, &te, fp32));
         int block = d.block ? d.block : te.block;
-        int rpl = d.rays_per_lane ? d.rays_per_lane : te.rpl;
+        int rpl = fp32 ? 1 : d.rays_per_lane ? d.rays_per_lane : te.rpl;
         std::vector<Launch> seq;
-        RGCHK(persistent_rk4_seq(p, a, block, rpl, seq));
+        RGCHK(persistent_rk4_seq(p, a, block, rpl, seq, fp32));
         p->last.block = block;
         p->last.rays_per_lane = rpl;
         return run_seq(p, seq, graph, s);

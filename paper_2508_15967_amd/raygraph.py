@@ -54,6 +54,7 @@ RG_ADD, RG_SUB, RG_MUL, RG_DIV = range(4)
  OP_SIN, OP_COS, OP_POWI, OP_SPLINE) = range(15)
 RK4, DOPRI54 = 0, 1
 PERSISTENT, PLAIN = 0, 1
+FP64, FP32 = 0, 1
 RAY_OK, RAY_EXITED_BOX, RAY_BUDGET, RAY_NONFINITE, RAY_STEP_UNDERFLOW = range(5)
 
 SYMBOLS = [
@@ -75,7 +76,8 @@ class RayGraphError(RuntimeError):
 
 class _CompileOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("want_adjoint", C.c_int32),
-                ("compile_only", C.c_int32), ("opt_level", C.c_int32), ("arch", C.c_char_p)]
+                ("compile_only", C.c_int32), ("opt_level", C.c_int32), ("arch", C.c_char_p),
+                ("fp32", C.c_int32)]
 
 
 class _ProgramInfo(C.Structure):
@@ -109,7 +111,7 @@ class TraceDesc(C.Structure):
                 ("checkpoint_every", C.c_int32), ("checkpoints", C.c_void_p),
                 ("mode", C.c_int32), ("use_hipgraph", C.c_int32), ("block", C.c_int32),
                 ("rays_per_lane", C.c_int32), ("compact_interval", C.c_int32),
-                ("attempts_out", C.c_void_p)]
+                ("attempts_out", C.c_void_p), ("precision", C.c_int32)]
 
 
 class AdjointDesc(C.Structure):
@@ -309,8 +311,9 @@ class Graph:
         return buf.value.decode()
 
     def compile(self, D: Node, want_adjoint: bool = False, compile_only: bool = False,
-                opt_level: int = 0) -> "Program":
-        o = _CompileOpts(C.sizeof(_CompileOpts), int(want_adjoint), int(compile_only), opt_level, None)
+                opt_level: int = 0, fp32: bool = False) -> "Program":
+        o = _CompileOpts(C.sizeof(_CompileOpts), int(want_adjoint), int(compile_only), opt_level, None,
+                         int(fp32))
         h = C.c_void_p()
         _chk(_lib.rg_compile(self.h, D.id, C.byref(o), C.byref(h)), "rg_compile")
         return Program(h, self.dim, list(self.param_lens), list(self.param_names))
@@ -383,7 +386,7 @@ class Program:
                   t0=None, store_every=0, traj=None, traj_D=None, x_out=None, k_out=None,
                   t_out=None, status_out=None, steps_out=None, checkpoint_every=0,
                   checkpoints=None, mode=PERSISTENT, use_hipgraph=False, block=0,
-                  rays_per_lane=0, compact_interval=0, attempts_out=None):
+                  rays_per_lane=0, compact_interval=0, attempts_out=None, precision=FP64):
         import torch
         f64, i32 = torch.float64, torch.int32
         for t, nm, dt_ in ((x0, "x0", f64), (k0, "k0", f64), (omega, "omega", f64), (t0, "t0", f64),
@@ -418,6 +421,7 @@ class Program:
         d.mode, d.use_hipgraph = int(mode), int(bool(use_hipgraph))
         d.block, d.rays_per_lane, d.compact_interval = int(block), int(rays_per_lane), int(compact_interval)
         d.attempts_out = _dptr(attempts_out)
+        d.precision = int(precision)
         return d
 
     def trace_desc(self, d: TraceDesc, stream=None):

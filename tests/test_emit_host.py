@@ -45,6 +45,19 @@ extern "C" void host_eval(int n, int ny, const double *y, const double *om, cons
         D[r] = rg_D(yy, om[r], 0.0, P);
     }
 }
+#ifdef HAS_F32
+extern "C" void host_eval32(int n, int ny, const float *y, const float *om, const double *const *pp,
+                            float *f) {
+    rg_P P; memset(&P, 0, sizeof P);
+    for (int i = 0; i < 8 && pp; i++) P.p[i] = pp[i];
+    for (int r = 0; r < n; r++) {
+        float yy[6], ff[6];
+        for (int c = 0; c < ny; c++) yy[c] = y[c * n + r];
+        rg_rhs(yy, om[r], 0.0f, P, ff);
+        for (int c = 0; c < ny; c++) f[c * n + r] = ff[c];
+    }
+}
+#endif
 #ifdef HAS_VJP
 extern "C" void host_vjp(int n, int ny, const double *y, const double *om, const double *const *pp,
                          const double *v, double *jv, double *gp) {
@@ -62,7 +75,7 @@ extern "C" void host_vjp(int n, int ny, const double *y, const double *om, const
 '''
 
 
-def _host_lib(prog, has_vjp, tmp):
+def _host_lib(prog, has_vjp, tmp, has_f32=False):
     with open(os.path.join(tmp, "functions.h"), "w") as f:
         f.write(prog.functions())
     src = os.path.join(tmp, "h.cpp")
@@ -70,7 +83,7 @@ def _host_lib(prog, has_vjp, tmp):
         f.write(HOST_HARNESS)
     so = os.path.join(tmp, "h.so")
     cmd = ["g++", "-O1", "-ffp-contract=off", "-fPIC", "-shared", "-I" + PRELUDE, "-I" + tmp, src,
-           "-o", so] + (["-DHAS_VJP"] if has_vjp else [])
+           "-o", so] + (["-DHAS_VJP"] if has_vjp else []) + (["-DHAS_F32"] if has_f32 else [])
     subprocess.run(cmd, check=True, capture_output=True)
     return C.CDLL(so)
 
@@ -125,3 +138,41 @@ def test_emitted_functions_match_oracle(oracle, cfg):
             go = oracle.param_vjp_points(w.medium, y, om, v)
             got = grad if cfg == "4" else gp[:16]
             assert np.abs(got - go).max() / np.abs(go).max() < 1e-12
+
+
+@pytest.mark.parametrize("cfg", ["1", "2", "3", "5", "cO", "cX"])
+def test_emitted_fp32_rhs(oracle, cfg):
+    """The single precision right-hand side (same graph, float arithmetic)
+    against the oracle's FP64 formulas at the same (float-representable)
+    points.  Each output is a short expression of the inputs evaluated in
+    float: its error is a modest multiple of the unit roundoff 2^-24 (about
+    6e-8) relative to the output scale, amplified by the expression's
+    conditioning; 5e-6 leaves margin for the cancellation in the cold-plasma
+    determinant near its cutoffs.  The cold-plasma determinant itself is a
+    sum of products several orders of magnitude larger than its value near
+    the cutoffs, and its partials lose correspondingly more: 1e-3 there."""
+    from paper_2508_15967_amd import media
+    w = {"cO": lambda: W.coldplasma("O"), "cX": lambda: W.coldplasma("X", x0=12.0)}.get(
+        cfg, lambda: W.make(cfg, 2048))()
+    g, D, params = media.build(w.medium)
+    prog = g.compile(D, compile_only=True, fp32=True)
+    rng = np.random.default_rng(5)
+    n = 400
+    y, om = _points(w, n, rng)
+    if cfg in ("2", "3"):
+        y[2] = rng.uniform(2.0, 18.0, n)  # inside the stratified layer (the launch plane has N = 1)
+    y32, om32 = y.astype(np.float32), om.astype(np.float32)
+    ny = 2 * w.dim
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, False, tmp, has_f32=True)
+        f = np.zeros((ny, n), dtype=np.float32)
+        lib.host_eval32(n, ny, C.c_void_p(y32.ctypes.data), C.c_void_p(om32.ctypes.data), _ptrs(params),
+                        C.c_void_p(f.ctypes.data))
+    fo, _, _ = oracle.eval_points(w.medium, np.ascontiguousarray(y32, dtype=np.float64),
+                                  np.ascontiguousarray(om32, dtype=np.float64), jac=False)
+    scale = np.abs(fo).max(axis=0)
+    err = (np.abs(f.astype(np.float64) - fo).max(axis=0) / scale).max()
+    print(cfg, "max relative error", err)
+    assert err < (1e-3 if cfg.startswith("c") else 5e-6)
+    # and not accidentally double precision
+    assert err > 1e-12
