@@ -259,7 +259,8 @@ def main():
             torch.linalg.vector_norm(x64, dim=0), min=1.0)
         result["fp32"] = {"value": steps32 / (ms32 * 1e-3), "unit": "ray-steps/s", "ms_per_trace": ms32,
                           "speedup_vs_fp64": fwd_ms / ms32, "launch": prog32.last_launch(),
-                          "max_rel_dev_x_vs_fp64": float(dx.max())}
+                          "median_rel_dev_x_vs_fp64": float(dx.median()),
+                          "frac_rays_dev_x_gt_1e-3": float((dx > 1e-3).double().mean())}
         outs["x_out"].copy_(x64)
         outs["k_out"].copy_(k64)
 
@@ -296,9 +297,14 @@ def main():
 
         m = args.cpu_rays
         if not m:
-            pilot = min(w.n, 4 * cores)
-            _, _, ps = oracle_run(pilot)
-            m = int(min(w.n, max(pilot, pilot * args.cpu_seconds / max(ps, 1e-3))))
+            # pilot runs grow until one takes a second, then one sized run
+            m = min(w.n, 4 * cores)
+            while True:
+                _, _, ps = oracle_run(m)
+                if ps >= 1.0 or m >= w.n:
+                    break
+                m = min(w.n, m * 8)
+            m = int(min(w.n, max(m, m * args.cpu_seconds / max(ps, 1e-3))))
         ws, ro, cs = oracle_run(m)
         crs = int(ro["steps"].astype(np.int64).sum())
         result["cpu_baseline"] = {"value": crs / cs, "unit": "ray-steps/s" + (" (fwd+adj)" if adjoint else ""),

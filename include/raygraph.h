@@ -246,7 +246,9 @@ typedef struct {
 
 /* Trace n_rays rays.  RK4 runs exactly n_steps steps per ray (fewer if it
  * stops, see status); DOPRI54 runs until the box is left, the budget is used
- * or t_end is reached.  Requires a program compiled without compile_only. */
+ * or t_end is reached.  Requires a program compiled without compile_only.
+ * n_rays = 0 returns RG_OK without touching any ray buffer (they may then
+ * be NULL). */
 rg_status rg_trace_rays(rg_program *p, const rg_trace_desc *d, void *hip_stream);
 
 typedef struct {

@@ -88,6 +88,7 @@ static rg_status kernel(rg_program *p, const char *name, hipFunction_t *f) {
 // `bytes` that follow it; anything else (host memory, a stale pointer, a
 // buffer too small for the rays) is rejected before any launch.
 static rg_status check_dev(const void *ptr, size_t bytes, const char *what) {
+    if (bytes == 0) return RG_OK;  // never touched (zero rays); may be NULL
     if (!ptr) return fail(RG_EINVAL, std::string(what) + " is NULL");
     hipPointerAttribute_t at;
     std::memset(&at, 0, sizeof at);
@@ -375,7 +376,7 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     auto it = p->tune.find(key);
     if (it != p->tune.end()) { *out = it->second; p->last.tuned = 1; return RG_OK; }
     rg_kargs t = a;
-    t.n_steps = std::min(a.n_steps, 16);
+    t.n_steps = std::min(a.n_steps, 128);  // long enough to rank the candidates above timer noise
     t.store_every = 0;
     t.traj = nullptr;
     t.traj_D = nullptr;

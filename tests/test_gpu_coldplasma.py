@@ -20,7 +20,9 @@ def test_O_mode_parity_and_cutoff(oracle):
     """O-mode from x = -5 crosses the upper-hybrid layer, turns at the plasma
     cut-off x = 10 (eq. 4 parabola) and comes back: GPU = oracle = parabola."""
     w = W.coldplasma("O", n_rays=256, dt=1e-2, n_steps=4000)
-    w.store_every = 100
+    # snapshots every 0.1 time units: near the turn x(t) ~ x_turn - 0.025 (t - t*)^2,
+    # so the largest sampled x is within 1e-4 of the turning point
+    w.store_every = 10
     g = U.gpu_trace(w, store=True, store_D=True)
     o = oracle.trace(w, store=True)
     ex, ek = U.traj_errors(g["traj"], o["traj"], w.omega, w.dim)
