@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0 = auto)")
-    ap.add_argument("--traffic", default="", help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--traffic", default="",
+                    help="HBM-traffic summary (default: profiles/traffic_<kernel>_<workload>.txt)")
     ap.add_argument("--block", type=int, default=0, help="fix the block size (0 = autotuned)")
     ap.add_argument("--rpl", type=int, default=0, help="fix rays per lane (0 = autotuned)")
     ap.add_argument("--compact", type=int, default=0, help="fix the compaction interval (0 = autotuned)")
@@ -126,6 +127,10 @@ def main():
         torch.mul(outs["x_out"] - adj["tx"], 2.0, out=adj["lx"])
         prog.adjoint_desc(desc, adj["lx"], None, adj["gx0"], adj["gk0"], adj["gp"], stream)
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress(f"workload {w.name}: {n} rays, compiled in {compile_s:.1f} s")
     # warmup (includes autotuning and hipGraph capture on the first call)
     t0 = time.time()
     for _ in range(max(args.warmup, 1)):
@@ -143,6 +148,7 @@ def main():
            for _ in range(args.steps)] if adjoint else []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    progress(f"warmup done in {warm_s:.1f} s")
     for i in range(args.steps):
         ev[i][0].record(stream)
         fwd()
@@ -152,6 +158,7 @@ def main():
             bwd()
             evb[i][1].record(stream)
     torch.cuda.synchronize()
+    progress("timed steps done")
     wall = time.perf_counter() - t0
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evb])) if adjoint else 0.0
@@ -170,18 +177,34 @@ def main():
         attempts = int(outs["attempts_out"].cpu().numpy().astype(np.int64).sum())
         flops_alg = info["dopri_attempt_flops_alg"] * attempts
         flops_iss = info["dopri_attempt_flops_issued"] * attempts
-    kernel_ms = fwd_ms
     if adjoint:
         flops_alg_adj = info["adj_step_flops_alg"] * ray_steps
         flops_iss_adj = info["adj_step_flops_issued"] * ray_steps
-    achieved = flops_alg / (kernel_ms * 1e-3) / 1e12
-    achieved_iss = flops_iss / (kernel_ms * 1e-3) / 1e12
+    # the roofline entry is for the dominant kernel of one step
+    if w.integrator == W.RK4:
+        kname = "rg_rk4_r%d" % launch["rays_per_lane"]
+    else:
+        kname = "rg_dopri_persistent"
+    kernel_ms, k_alg, k_iss = fwd_ms, flops_alg, flops_iss
+    if adjoint and bwd_ms > fwd_ms:
+        kname, kernel_ms, k_alg, k_iss = "rg_rk4_adjoint", bwd_ms, flops_alg_adj, flops_iss_adj
+    achieved = k_alg / (kernel_ms * 1e-3) / 1e12
+    achieved_iss = k_iss / (kernel_ms * 1e-3) / 1e12
 
+    # HBM bytes per launch of that kernel from the rocprofv3 FETCH_SIZE and
+    # WRITE_SIZE passes (calibrated against a copy of known size), valid
+    # only for the source they were taken on
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        tj = json.load(open(args.traffic))
-        if tj.get("source_hash") == info["source_hash"] and tj.get("config") == args.config:
-            traffic = tj.get("bytes_per_launch")
+    tfile = args.traffic or os.path.join(ROOT, "profiles", f"traffic_{kname}_{w.name}.txt")
+    if os.path.exists(tfile):
+        kv = {}
+        for line in open(tfile):
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+        if (kv.get("source_hash") == "%016x" % info["source_hash"] and kv.get("kernel") == kname
+                and kv.get("workload") == w.name):
+            traffic = float(kv["hbm_bytes_per_launch"])
 
     result = {
         "metric": "FP64 ray-steps/s (persistent fused RK4, one launch per trace)",
@@ -193,10 +216,11 @@ def main():
                    "ray_steps_per_trace": ray_steps, "adjoint": adjoint},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "rg_rk4_r%d" % launch["rays_per_lane"] if w.integrator == W.RK4 else "rg_dopri_persistent",
-                     "kernel_ms": kernel_ms, "flops_per_ray_step_alg": flops_alg / max(ray_steps, 1),
+                     "kernel": kname, "kernel_ms": kernel_ms,
+                     "flops_per_ray_step_alg": k_alg / max(ray_steps, 1),
                      "achieved_issued": achieved_iss, "frac_issued": achieved_iss / PEAK_FP64_TFLOPS},
         "launch": launch, "compile_s": compile_s, "warmup_s": warm_s,
+        "source_hash": "%016x" % info["source_hash"],
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
     }
     if adjoint:
@@ -214,6 +238,7 @@ def main():
     # hand-derived-derivative kernels for the anisotropic medium (speed
     # reference for the compiled kernels on the same inputs)
     if args.config == "5":
+        progress("hand-derived kernels")
         from paper_2508_15967_amd import hand
         hm = hand.medium_struct(w.medium)
         hx, hk = torch.empty_like(x0), torch.empty_like(k0)
@@ -266,6 +291,7 @@ def main():
 
     # plain one-launch-per-step comparator on the same GPU and inputs
     if not args.no_plain:
+        progress("plain comparator")
         pdesc = prog.make_desc(x0, k0, om, pt, mode=rgb.PLAIN, use_hipgraph=False, **kw, **outs)
         prog.trace_desc(pdesc, stream)  # warm
         torch.cuda.synchronize()
@@ -277,11 +303,13 @@ def main():
         psteps = int(outs["steps_out"].cpu().numpy().astype(np.int64).sum())
         result["plain"] = {"value": psteps / pw, "ms_per_trace": pw * 1e3,
                            "launches_per_trace": w.n_steps + 2 if w.integrator == W.RK4 else None}
-        result["speedup_vs_plain"] = (ray_steps / (ms_per_step * 1e-3)) / (psteps / pw)
+        # forward against forward (the plain form has no adjoint)
+        result["speedup_vs_plain"] = (pw * 1e3 / psteps) / (fwd_ms / ray_steps)
 
     # CPU oracle on a bounded sample of the same workload: a pilot run sizes
     # the sample to about --cpu-seconds of work on all host cores
     if not args.no_cpu:
+        progress("oracle sample on the host cores")
         from oracle import pyoracle
         pyoracle.build(force=False)
         cores = pyoracle.threads()
