@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <set>
 #include <sstream>
 #include <stdexcept>
 
@@ -312,6 +314,166 @@ std::vector<uint32_t> Graph::adjoints(const std::vector<uint32_t> &outs,
     }
     adj.resize(nodes_.size(), NONE);
     return adj;
+}
+
+// ------------------------------------------------------ factor products ---
+
+std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots) {
+    const std::vector<uint32_t> order = reachable(roots);
+    const size_t N0 = nodes_.size();
+    auto is_prod = [&](uint32_t n) {
+        const Node &d = nodes_[n];
+        return d.op == MUL || (d.op == NEG && nodes_[d.a].op == MUL);
+    };
+    // a product is rebuilt on its own where its value is used by a
+    // non-product or is a root; elsewhere it is folded into its consumers
+    std::vector<char> top(N0, 0);
+    for (uint32_t r : roots)
+        if (r != NONE) top[r] = 1;
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM || is_prod(n)) continue;
+        if (d.a != NONE) top[d.a] = 1;
+        if (d.b != NONE) top[d.b] = 1;
+    }
+    // flattened factor count (bounded: a product of powers could double at
+    // every level)
+    const size_t kMaxFactors = 32;
+    std::vector<size_t> fsize(N0, 1);
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == MUL) fsize[n] = std::min(kMaxFactors + 1, fsize[d.a] + fsize[d.b]);
+        else if (d.op == NEG && nodes_[d.a].op == MUL) fsize[n] = fsize[d.a];
+    }
+    struct Prod {
+        uint32_t node;
+        double c;                   // folded constant factors and sign
+        std::vector<uint32_t> sym;  // leaf nodes, or kVirtual | pair index
+    };
+    const uint32_t kVirtual = 0x80000000u;
+    std::vector<Prod> prods;
+    std::vector<int> prod_of(N0, -1);
+    for (uint32_t n : order) {
+        if (!is_prod(n) || !top[n]) continue;
+        if (fsize[n] > kMaxFactors) return roots;  // leave such graphs alone
+        Prod P{n, 1.0, {}};
+        std::vector<uint32_t> stack{n};
+        while (!stack.empty()) {
+            const uint32_t m = stack.back();
+            stack.pop_back();
+            const Node &d = nodes_[m];
+            if (d.op == MUL) {
+                stack.push_back(d.b);
+                stack.push_back(d.a);
+            } else if (d.op == NEG && nodes_[d.a].op == MUL) {
+                P.c = -P.c;
+                stack.push_back(d.a);
+            } else if (d.op == CONST) {
+                P.c *= d.val;
+            } else {
+                P.sym.push_back(m);
+            }
+        }
+        // a constant factor takes part in the pairing (a scaled common
+        // factor such as 2/D_omega is then formed once); a sign stays apart
+        // (negation is free as an operand modifier)
+        if (P.c != 1.0 && P.c != -1.0) {
+            P.sym.push_back(constant(std::fabs(P.c)));
+            P.c = P.c < 0 ? -1.0 : 1.0;
+        }
+        std::sort(P.sym.begin(), P.sym.end());
+        prod_of[n] = (int)prods.size();
+        prods.push_back(std::move(P));
+    }
+    // greedy pairing (most shared pair first, ties to the smaller pair)
+    std::vector<std::pair<uint32_t, uint32_t>> pairs;
+    for (;;) {
+        std::map<std::pair<uint32_t, uint32_t>, int> count;
+        for (const Prod &P : prods) {
+            std::set<std::pair<uint32_t, uint32_t>> here;
+            for (size_t i = 0; i < P.sym.size(); i++)
+                for (size_t j = i + 1; j < P.sym.size(); j++) here.insert({P.sym[i], P.sym[j]});
+            for (const auto &pr : here) count[pr]++;
+        }
+        std::pair<uint32_t, uint32_t> best{0, 0};
+        int bc = 1;
+        for (const auto &kv : count)
+            if (kv.second > bc) {
+                bc = kv.second;
+                best = kv.first;
+            }
+        if (bc < 2) break;
+        const uint32_t v = kVirtual | (uint32_t)pairs.size();
+        pairs.push_back(best);
+        for (Prod &P : prods) {
+            auto ia = std::find(P.sym.begin(), P.sym.end(), best.first);
+            if (ia == P.sym.end()) continue;
+            auto ib = std::find(ia + 1, P.sym.end(), best.second);
+            if (ib == P.sym.end()) continue;
+            P.sym.erase(ib);
+            P.sym.erase(ia);
+            P.sym.push_back(v);
+            std::sort(P.sym.begin(), P.sym.end());
+        }
+    }
+    // factors are multiplied in order of variability: constants, then what
+    // depends only on omega, t and parameters (invariant along a ray: the
+    // compiler hoists that part of the product out of the time loop), then
+    // what depends on the state or the seeds
+    std::vector<int> rank(N0, 0);
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == VAR) rank[n] = (d.aux / 8 == VK_OMEGA || d.aux / 8 == VK_T) ? 1 : 2;
+        else if (d.op == PARAM) rank[n] = 1;
+        else if (d.op != CONST)
+            rank[n] = std::max(d.a != NONE ? rank[d.a] : 0, d.b != NONE ? rank[d.b] : 0);
+    }
+    std::function<int(uint32_t)> srank = [&](uint32_t s2) -> int {
+        if (s2 & kVirtual) {
+            const auto &pr = pairs[s2 & ~kVirtual];
+            return std::max(srank(pr.first), srank(pr.second));
+        }
+        return s2 < N0 ? rank[s2] : 0;  // new nodes here are folded constants
+    };
+    for (Prod &P : prods)
+        std::stable_sort(P.sym.begin(), P.sym.end(),
+                         [&](uint32_t x, uint32_t y) { return srank(x) < srank(y); });
+    // rebuild in topological order
+    std::vector<uint32_t> nw(N0, NONE), vnew(pairs.size(), NONE);
+    std::function<uint32_t(uint32_t)> get = [&](uint32_t s) -> uint32_t {
+        if (!(s & kVirtual)) return nodes_[s].op == CONST ? s : nw[s];  // folded constants may be new
+        const uint32_t i = s & ~kVirtual;
+        if (vnew[i] == NONE) vnew[i] = mul(get(pairs[i].first), get(pairs[i].second));
+        return vnew[i];
+    };
+    for (uint32_t n : order) {
+        const Node d = nodes_[n];  // copy: factories may grow nodes_
+        if (d.op == CONST || d.op == VAR || d.op == PARAM) {
+            nw[n] = n;
+            continue;
+        }
+        if (is_prod(n)) {
+            if (prod_of[n] < 0) continue;  // folded into its consumers
+            const Prod &P = prods[prod_of[n]];
+            uint32_t acc = NONE;
+            for (uint32_t s2 : P.sym) acc = acc == NONE ? get(s2) : mul(acc, get(s2));
+            nw[n] = acc == NONE ? constant(P.c) : P.c < 0 ? neg(acc) : acc;
+            continue;
+        }
+        const uint32_t a = d.a != NONE ? nw[d.a] : NONE, b = d.b != NONE ? nw[d.b] : NONE;
+        switch (d.op) {
+        case ADD: nw[n] = add(a, b); break;
+        case SUB: nw[n] = sub(a, b); break;
+        case DIV: nw[n] = div(a, b); break;
+        case NEG: nw[n] = neg(a); break;
+        case POWI: nw[n] = powi(a, d.aux); break;
+        case SPLINE: nw[n] = spline((uint32_t)d.val, d.aux / 4, d.aux % 4, a, b); break;
+        default: nw[n] = unary(d.op, a); break;
+        }
+    }
+    std::vector<uint32_t> out(roots.size(), NONE);
+    for (size_t i = 0; i < roots.size(); i++) out[i] = roots[i] == NONE ? NONE : nw[roots[i]];
+    return out;
 }
 
 // -------------------------------------------------------------- evaluate ---

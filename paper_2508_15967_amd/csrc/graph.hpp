@@ -78,6 +78,15 @@ public:
     std::vector<uint32_t> adjoints(const std::vector<uint32_t> &outs,
                                    const std::vector<uint32_t> &seeds);
 
+    // Products re-associated: every maximal product (a MUL or a negated MUL
+    // whose value is used by something other than a product, or a root) is
+    // flattened into its factors, constant factors are folded into one, the
+    // factor pairs that two or more products share are formed once (greedy,
+    // most shared pair first) and each product is rebuilt from them.  Other
+    // nodes are rebuilt on the new operands.  Returns the roots' new nodes
+    // (the old ones stay valid).  Reassociation changes rounding only.
+    std::vector<uint32_t> factor_products(const std::vector<uint32_t> &roots);
+
     bool is_const(uint32_t n) const { return nodes_[n].op == CONST; }
     bool is_const(uint32_t n, double v) const {
         return nodes_[n].op == CONST && nodes_[n].val == v;

@@ -11,6 +11,7 @@
 #include <hip/hiprtc.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include <chrono>
 #include <cstring>
@@ -39,6 +40,24 @@ static std::string int_array(const char *name, const std::vector<int> &v) {
     for (size_t i = 0; i < v.size(); i++) os << (i ? ", " : "") << v[i];
     os << "};\n";
     return os.str();
+}
+
+// Products of every function are re-associated before emission (shared
+// factor pairs formed once; see Graph::factor_products).
+static void factor_spec(Graph &g, FunctionSpec &spec) {
+    std::vector<uint32_t> roots;
+    for (const Output &o : spec.outputs) roots.push_back(o.node);
+    for (const SplineSeed &s : spec.spline_seeds) {
+        roots.push_back(s.seed);
+        roots.push_back(s.spline_node);
+    }
+    const std::vector<uint32_t> nr = g.factor_products(roots);
+    size_t k = 0;
+    for (Output &o : spec.outputs) o.node = nr[k++];
+    for (SplineSeed &s : spec.spline_seeds) {
+        s.seed = nr[k++];
+        s.spline_node = nr[k++];
+    }
 }
 
 rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_program *p) {
@@ -123,6 +142,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "RG_FN void rg_rhs(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, double *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
+        factor_spec(g, spec);
         fs << emit_function(g, spec, table_slot, &fl_rhs);
     }
     if (opts.fp32) {
@@ -137,6 +157,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P, float *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         Flops fl32;
+        factor_spec(g, spec);
         fs << emit_function(g, spec, table_slot, &fl32);
         p->has_f32 = true;
     }
@@ -147,6 +168,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
         spec.returns_value = true;
+        factor_spec(g, spec);
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
     {
@@ -159,6 +181,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < d; i++)
             spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
         Flops fl_dk;
+        factor_spec(g, spec);
         fs << emit_function(g, spec, table_slot, &fl_dk);
     }
     p->info.n_nodes_rhs = fl_rhs.ops;
@@ -191,6 +214,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             const Node &nd = g.node(n);
             if (nd.op == SPLINE) spec.spline_seeds.push_back({n, A(n)});
         }
+        factor_spec(g, spec);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
     }
