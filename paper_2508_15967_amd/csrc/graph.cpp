@@ -406,14 +406,17 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots)
         const uint32_t v = kVirtual | (uint32_t)pairs.size();
         pairs.push_back(best);
         for (Prod &P : prods) {
-            auto ia = std::find(P.sym.begin(), P.sym.end(), best.first);
-            if (ia == P.sym.end()) continue;
-            auto ib = std::find(ia + 1, P.sym.end(), best.second);
-            if (ib == P.sym.end()) continue;
-            P.sym.erase(ib);
-            P.sym.erase(ia);
-            P.sym.push_back(v);
-            std::sort(P.sym.begin(), P.sym.end());
+            // every disjoint occurrence (x y x y holds the pair twice)
+            for (;;) {
+                auto ia = std::find(P.sym.begin(), P.sym.end(), best.first);
+                if (ia == P.sym.end()) break;
+                auto ib = std::find(ia + 1, P.sym.end(), best.second);
+                if (ib == P.sym.end()) break;
+                P.sym.erase(ib);
+                P.sym.erase(ia);
+                P.sym.push_back(v);
+                std::sort(P.sym.begin(), P.sym.end());
+            }
         }
     }
     // factors are multiplied in order of variability: constants, then what
@@ -464,6 +467,164 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots)
         switch (d.op) {
         case ADD: nw[n] = add(a, b); break;
         case SUB: nw[n] = sub(a, b); break;
+        case DIV: nw[n] = div(a, b); break;
+        case NEG: nw[n] = neg(a); break;
+        case POWI: nw[n] = powi(a, d.aux); break;
+        case SPLINE: nw[n] = spline((uint32_t)d.val, d.aux / 4, d.aux % 4, a, b); break;
+        default: nw[n] = unary(d.op, a); break;
+        }
+    }
+    std::vector<uint32_t> out(roots.size(), NONE);
+    for (size_t i = 0; i < roots.size(); i++) out[i] = roots[i] == NONE ? NONE : nw[roots[i]];
+    return out;
+}
+
+std::vector<uint32_t> Graph::factor_sums(const std::vector<uint32_t> &roots) {
+    const std::vector<uint32_t> order = reachable(roots);
+    const size_t N0 = nodes_.size();
+    auto is_sum = [&](uint32_t n) {
+        const Node &d = nodes_[n];
+        return d.op == ADD || d.op == SUB ||
+               (d.op == NEG && (nodes_[d.a].op == ADD || nodes_[d.a].op == SUB));
+    };
+    std::vector<char> top(N0, 0);
+    for (uint32_t r : roots)
+        if (r != NONE) top[r] = 1;
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM || is_sum(n)) continue;
+        if (d.a != NONE) top[d.a] = 1;
+        if (d.b != NONE) top[d.b] = 1;
+    }
+    const size_t kMaxTerms = 4096;  // a sum of shared sums could double at every level
+    std::vector<size_t> tsize(N0, 1);
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == ADD || d.op == SUB) tsize[n] = std::min(kMaxTerms + 1, tsize[d.a] + tsize[d.b]);
+        else if (is_sum(n)) tsize[n] = tsize[d.a];
+    }
+    // a symbol is (node or kVirtual | pair index) * 2 + (1 if negated)
+    const uint64_t kVirtual = 0x80000000ull;
+    struct Sum {
+        uint32_t node;
+        double c;                   // folded constant terms
+        std::vector<uint64_t> sym;  // signed terms
+    };
+    std::vector<Sum> sums;
+    std::vector<int> sum_of(N0, -1);
+    for (uint32_t n : order) {
+        if (!is_sum(n) || !top[n]) continue;
+        if (tsize[n] > kMaxTerms) return roots;  // leave such graphs alone
+        Sum S{n, 0.0, {}};
+        std::vector<std::pair<uint32_t, int>> stack{{n, 1}};
+        while (!stack.empty()) {
+            const auto [m, sg] = stack.back();
+            stack.pop_back();
+            const Node &d = nodes_[m];
+            if (d.op == ADD) {
+                stack.push_back({d.b, sg});
+                stack.push_back({d.a, sg});
+            } else if (d.op == SUB) {
+                stack.push_back({d.b, -sg});
+                stack.push_back({d.a, sg});
+            } else if (d.op == NEG && is_sum(m)) {
+                stack.push_back({d.a, -sg});
+            } else if (d.op == CONST) {
+                S.c += sg * d.val;
+            } else {
+                S.sym.push_back((uint64_t)m * 2 + (sg < 0 ? 1 : 0));
+            }
+        }
+        std::sort(S.sym.begin(), S.sym.end());
+        sum_of[n] = (int)sums.size();
+        sums.push_back(std::move(S));
+    }
+    // greedy pairing of terms; a pair and its negation are the same node
+    // (key: first term positive), each occurrence keeps its overall sign
+    auto id_of = [](uint64_t s) { return s >> 1; };
+    auto neg_of = [](uint64_t s) { return (s & 1) != 0; };
+    struct Pair {
+        uint64_t a, b;  // a positive
+    };
+    std::vector<Pair> pairs;
+    auto key = [&](uint64_t x, uint64_t y) {
+        if (id_of(y) < id_of(x) || (id_of(y) == id_of(x) && y < x)) std::swap(x, y);
+        const bool flip = neg_of(x);
+        if (flip) {
+            x ^= 1;
+            y ^= 1;
+        }
+        return std::make_pair(std::make_pair(x, y), flip);
+    };
+    for (;;) {
+        std::map<std::pair<uint64_t, uint64_t>, int> count;
+        for (const Sum &S : sums) {
+            std::set<std::pair<uint64_t, uint64_t>> here;
+            for (size_t i = 0; i < S.sym.size(); i++)
+                for (size_t j = i + 1; j < S.sym.size(); j++) here.insert(key(S.sym[i], S.sym[j]).first);
+            for (const auto &pr : here) count[pr]++;
+        }
+        std::pair<uint64_t, uint64_t> best{0, 0};
+        int bc = 1;
+        for (const auto &kv : count)
+            if (kv.second > bc) {
+                bc = kv.second;
+                best = kv.first;
+            }
+        if (bc < 2) break;
+        const uint64_t v = (kVirtual | pairs.size()) * 2;
+        pairs.push_back(Pair{best.first, best.second});
+        for (Sum &S : sums) {
+            // every disjoint occurrence (x + y + x + y holds the pair twice)
+            for (bool found = true; found;) {
+                found = false;
+                for (size_t i = 0; i < S.sym.size() && !found; i++)
+                    for (size_t j = i + 1; j < S.sym.size() && !found; j++) {
+                        const auto k = key(S.sym[i], S.sym[j]);
+                        if (k.first != best) continue;
+                        S.sym.erase(S.sym.begin() + j);
+                        S.sym.erase(S.sym.begin() + i);
+                        S.sym.push_back(v | (k.second ? 1 : 0));
+                        found = true;
+                    }
+            }
+            std::sort(S.sym.begin(), S.sym.end());
+        }
+    }
+    std::vector<uint32_t> nw(N0, NONE), vnew(pairs.size(), NONE);
+    std::function<uint32_t(uint64_t)> get_abs = [&](uint64_t s) -> uint32_t {
+        const uint64_t id = id_of(s);
+        if (!(id & kVirtual)) return nodes_[id].op == CONST ? (uint32_t)id : nw[id];
+        const size_t i = (size_t)(id & ~kVirtual);
+        if (vnew[i] == NONE) {
+            const Pair &P = pairs[i];
+            const uint32_t a = get_abs(P.a), b = get_abs(P.b);
+            vnew[i] = neg_of(P.b) ? sub(a, b) : add(a, b);
+        }
+        return vnew[i];
+    };
+    for (uint32_t n : order) {
+        const Node d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM) {
+            nw[n] = n;
+            continue;
+        }
+        if (is_sum(n)) {
+            if (sum_of[n] < 0) continue;  // folded into its consumers
+            const Sum &S = sums[sum_of[n]];
+            uint32_t acc = NONE;
+            for (uint64_t s2 : S.sym) {
+                const uint32_t t = get_abs(s2);
+                if (acc == NONE) acc = neg_of(s2) ? neg(t) : t;
+                else acc = neg_of(s2) ? sub(acc, t) : add(acc, t);
+            }
+            if (S.c != 0.0) acc = acc == NONE ? constant(S.c) : add(constant(S.c), acc);
+            nw[n] = acc == NONE ? constant(0.0) : acc;
+            continue;
+        }
+        const uint32_t a = d.a != NONE ? nw[d.a] : NONE, b = d.b != NONE ? nw[d.b] : NONE;
+        switch (d.op) {
+        case MUL: nw[n] = mul(a, b); break;
         case DIV: nw[n] = div(a, b); break;
         case NEG: nw[n] = neg(a); break;
         case POWI: nw[n] = powi(a, d.aux); break;

@@ -87,6 +87,13 @@ public:
     // (the old ones stay valid).  Reassociation changes rounding only.
     std::vector<uint32_t> factor_products(const std::vector<uint32_t> &roots);
 
+    // The same for sums: every maximal sum (ADD/SUB chains, negations
+    // included) is flattened into signed terms, constant terms folded, term
+    // pairs shared by two or more sums formed once, and the sums rebuilt
+    // (a sum that reappears as a sub-sum of another is then one node, and
+    // x + x reduces to 2x).
+    std::vector<uint32_t> factor_sums(const std::vector<uint32_t> &roots);
+
     bool is_const(uint32_t n) const { return nodes_[n].op == CONST; }
     bool is_const(uint32_t n, double v) const {
         return nodes_[n].op == CONST && nodes_[n].val == v;

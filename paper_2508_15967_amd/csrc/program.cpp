@@ -51,7 +51,7 @@ static void factor_spec(Graph &g, FunctionSpec &spec) {
         roots.push_back(s.seed);
         roots.push_back(s.spline_node);
     }
-    const std::vector<uint32_t> nr = g.factor_products(roots);
+    const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(roots));
     size_t k = 0;
     for (Output &o : spec.outputs) o.node = nr[k++];
     for (SplineSeed &s : spec.spline_seeds) {

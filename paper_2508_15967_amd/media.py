@@ -71,9 +71,10 @@ def build(med: W.Medium) -> Tuple[rgb.Graph, rgb.Node, List[np.ndarray]]:
             m = [float(v) for v in med.mats[b]]  # xx xy xz yy yz zz
             r2 = _sum([(x[i] - float(c[i])) * (x[i] - float(c[i])) for i in range(3)])
             gb = (r2 * (-1.0 / float(med.widths[b]) ** 2)).exp()
-            q = (m[0] * (k[0] * k[0]) + m[3] * (k[1] * k[1]) + m[5] * (k[2] * k[2])
-                 + (2.0 * m[1]) * (k[0] * k[1]) + (2.0 * m[2]) * (k[0] * k[2])
-                 + (2.0 * m[4]) * (k[1] * k[2]))
+            # q = k . (M k)
+            M = [[m[0], m[1], m[2]], [m[1], m[3], m[4]], [m[2], m[4], m[5]]]
+            mk = [_sum([M[i][j] * k[j] for j in range(3)]) for i in range(3)]
+            q = _sum([k[i] * mk[i] for i in range(3)])
             terms.append(g.elem(pid, b) * gb * q)
         D = kk - w2 + _sum(terms)
     elif med.kind == W.COLDPLASMA:
