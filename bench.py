@@ -334,6 +334,10 @@ def main():
                 m = min(w.n, m * 8)
             m = int(min(w.n, max(m, m * args.cpu_seconds / max(ps, 1e-3))))
         ws, ro, cs = oracle_run(m)
+        if not args.cpu_rays and cs < 0.5 * args.cpu_seconds and m < w.n:
+            # the pilots' per-ray time was off (start-up costs): size again
+            m = int(min(w.n, m * args.cpu_seconds / max(cs, 1e-3)))
+            ws, ro, cs = oracle_run(m)
         crs = int(ro["steps"].astype(np.int64).sum())
         result["cpu_baseline"] = {"value": crs / cs, "unit": "ray-steps/s" + (" (fwd+adj)" if adjoint else ""),
                                   "cores": cores, "kind": "oracle",
