@@ -17,14 +17,14 @@ const IssuedWeights &issued_weights() {
     // (hipcc --offload-arch=gfx950 -O3 -ffp-contract=off): v_fma_f64 and
     // v_div_fmas_f64 = 2; v_add_f64, v_mul_f64, v_rcp_f64, v_rsq_f64 = 1;
     // compares, class tests, ldexp/frexp, rounding, conversions and selects = 0.
-    //   exp: 13 fma + 1 mul              = 27
+    //   exp (rg_exp, table-driven): 7 fma + 2 mul = 16
     //   div: 5 fma + div_fmas + mul + rcp = 14
     //   sqrt: 7 fma + 2 mul + rsq         = 17
     //   log: 14 fma + 43 add + 7 mul + rcp = 79
     //   sin/cos: 24 fma + 56 add + 11 mul = 115
     //   pow: 42 fma + 70 add + 11 mul + rcp = 166
     //   rg_rcp (reciprocal, rcp + two Newton steps): rcp + 4 fma = 9
-    static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 27.0, /*log*/ 79.0, /*sqrt*/ 17.0,
+    static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 16.0, /*log*/ 79.0, /*sqrt*/ 17.0,
                                  /*sincos*/ 115.0, /*pow*/ 166.0, /*rcp*/ 9.0};
     return w;
 }
@@ -302,7 +302,7 @@ struct Emitter {
             }
             break;
         case NEG: e = "-" + A; break;
-        case EXP: e = fn("exp") + "(" + A + ")"; count(EXP); break;
+        case EXP: e = (f32 ? "expf(" : "rg_exp(") + A + ")"; count(EXP); break;
         case LOG: e = fn("log") + "(" + A + ")"; count(LOG); break;
         case SQRT: e = fn("sqrt") + "(" + A + ")"; count(SQRT); break;
         case SIN: e = fn("sin") + "(" + A + ")"; count(SIN); break;

@@ -69,14 +69,26 @@ struct rg_GA {
 
 #include "rg_functions.h"
 
+#if RG_USES_EXP
+__constant__ double rg_exp_const[64] = {RG_EXP_TABLE_VALUES};
+#endif
+
+// Copies the spline tables and the exponential's table into LDS (every
+// thread of the workgroup must call it).
 __device__ __forceinline__ void rg_stage_tables(const rg_kargs &a) {
 #if RG_NSPLTAB > 0
     for (int k = 0; k < RG_NSPLTAB; k++) {
         const double *src = a.params[rg_spl_param[k]];
         for (int i = threadIdx.x; i < rg_spl_len[k]; i += blockDim.x) rg_spl_lds[rg_spl_off[k] + i] = src[i];
     }
+#endif
+#if RG_USES_EXP
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) rg_exp_lds[i] = rg_exp_const[i];
+#endif
+#if RG_NSPLTAB > 0 || RG_USES_EXP
     __syncthreads();
 #endif
+    (void)a;
 }
 
 __device__ __forceinline__ rg_P rg_params(const rg_kargs &a) {

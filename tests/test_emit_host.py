@@ -176,3 +176,74 @@ def test_emitted_fp32_rhs(oracle, cfg):
     assert err < (1e-3 if cfg.startswith("c") else 5e-6)
     # and not accidentally double precision
     assert err > 1e-12
+
+
+def _exp_points(rng, n):
+    x = np.concatenate([rng.uniform(-745.0, 709.7, n), rng.uniform(-30.0, 30.0, n),
+                        rng.uniform(-1.0, 1.0, n), (rng.random(n) - 0.5) * 1e-3])
+    special = np.array([0.0, -0.0, 709.78, 709.79, -745.0, -745.2, -1e5, -1e300, 1e300, 1100.0, 1101.0,
+                        -np.inf, np.inf, np.nan])
+    return x, special
+
+
+def _exp_reference(x):
+    """e^x correctly rounded to double (60-digit decimal arithmetic)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    out = np.empty_like(x)
+    for i, v in enumerate(x):
+        out[i] = float(Decimal(float(v)).exp())
+    return out
+
+
+def _exp_ulps(got, ref):
+    with np.errstate(invalid="ignore", over="ignore"):
+        sp = np.spacing(np.abs(ref))
+        sp = np.where(ref == 0.0, 2.0 ** -1074, sp)
+        return np.abs(got - ref) / sp
+
+
+def test_exp_table_matches_generator():
+    """The constants in rg_prelude.h are the generator's output."""
+    import importlib.util
+    path = os.path.join(PRELUDE, "gen_exp_table.py")
+    spec = importlib.util.spec_from_file_location("gen_exp_table", path)
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    text = open(os.path.join(PRELUDE, "rg_prelude.h")).read()
+    assert gen.block() in text
+
+
+def test_exp_host_accuracy():
+    """rg_exp (table-driven, host build of the same code) within 1.5 ulp of
+    the correctly rounded e^x, and exact special cases: overflow to +inf,
+    underflow to 0, e^(+-inf), NaN."""
+    from paper_2508_15967_amd import raygraph as rgb
+    g = rgb.Graph(2)
+    D = g.omega * g.x(0).exp()   # D = omega e^x0, evaluated at omega = 1
+    prog = g.compile(D, compile_only=True)
+    rng = np.random.default_rng(17)
+    x, special = _exp_points(rng, 5000)
+    xs = np.concatenate([x, special])
+    n = xs.size
+    y = np.zeros((4, n))
+    y[0] = xs
+    y[2] = 1.0
+    om = np.ones(n)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, False, tmp)
+        f = np.zeros((4, n))
+        Dv = np.zeros(n)
+        lib.host_eval(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), _ptrs([]),
+                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+    ref = _exp_reference(x)
+    ulps = _exp_ulps(Dv[:x.size], ref)
+    assert ulps.max() <= 1.5, ulps.max()
+    got_sp = Dv[x.size:]
+    with np.errstate(over="ignore"):
+        ref_sp = np.exp(special)
+    same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
+    # the finite specials are compared within the same bound
+    fin = np.isfinite(ref_sp) & (ref_sp > 0)
+    same |= fin & (_exp_ulps(got_sp, ref_sp) <= 1.5)
+    assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))

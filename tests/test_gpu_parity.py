@@ -145,6 +145,33 @@ def test_reciprocal_within_one_ulp():
     assert ulps.max() <= 1.0, ulps.max()
 
 
+def test_exp_within_ulps():
+    """The device rg_exp (table in LDS) within 1.5 ulp of the correctly
+    rounded e^x, with exact overflow/underflow/inf/NaN behaviour:
+    D = omega e^x0 evaluated at omega = 1."""
+    from paper_2508_15967_amd import raygraph as rgb
+    from tests.test_emit_host import _exp_points, _exp_reference, _exp_ulps
+    torch = U.torch_mod()
+    g = rgb.Graph(2)
+    prog = g.compile(g.omega * g.x(0).exp())
+    x, special = _exp_points(np.random.default_rng(17), 5000)
+    xs = np.concatenate([x, special])
+    y = np.zeros((4, xs.size))
+    y[0] = xs
+    y[2] = 1.0
+    _, D = prog.eval(U.dev(y), U.dev(np.ones(xs.size)))
+    torch.cuda.synchronize()
+    Dv = D.cpu().numpy()
+    ulps = _exp_ulps(Dv[:x.size], _exp_reference(x))
+    assert ulps.max() <= 1.5, ulps.max()
+    got_sp = Dv[x.size:]
+    with np.errstate(over="ignore"):
+        ref_sp = np.exp(special)
+    same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
+    same |= np.isfinite(ref_sp) & (ref_sp > 0) & (_exp_ulps(got_sp, ref_sp) <= 1.5)
+    assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+
+
 @pytest.mark.parametrize("cfg", ["1", "4", "5"])
 def test_newton_launch_conditions_match_oracle(oracle, cfg):
     """GPU Newton solve of D = 0 for k_x (rg_solve_k) against the oracle's
