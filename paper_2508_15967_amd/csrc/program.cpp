@@ -44,7 +44,8 @@ static std::string int_array(const char *name, const std::vector<int> &v) {
 
 // Products of every function are re-associated before emission (shared
 // factor pairs formed once; see Graph::factor_products).
-static void factor_spec(Graph &g, FunctionSpec &spec) {
+static void factor_spec(Graph &g, FunctionSpec &spec, bool table_exp) {
+    spec.table_exp = table_exp;
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);
     for (const SplineSeed &s : spec.spline_seeds) {
@@ -132,6 +133,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     // stage states in LDS (3 * 2*dim doubles per lane), next to the spline
     // tables and their gradient accumulator.
     p->rolled = n_consts > 32 && p->spl_total <= 4096;
+    // The table-driven exponential saves instructions but waits on an LDS
+    // read; the rolled kernels run at 2-3 waves per SIMD, too few to hide
+    // that latency, and keep the library exponential (pure ALU).
 
     // ---- emit rhs and D
     std::ostringstream fs;
@@ -142,7 +146,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "RG_FN void rg_rhs(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, double *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
-        factor_spec(g, spec);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_rhs);
     }
     if (opts.fp32) {
@@ -157,7 +161,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P, float *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         Flops fl32;
-        factor_spec(g, spec);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl32);
         p->has_f32 = true;
     }
@@ -168,7 +172,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
         spec.returns_value = true;
-        factor_spec(g, spec);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
     {
@@ -181,7 +185,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < d; i++)
             spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
         Flops fl_dk;
-        factor_spec(g, spec);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_dk);
     }
     p->info.n_nodes_rhs = fl_rhs.ops;
@@ -214,7 +218,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             const Node &nd = g.node(n);
             if (nd.op == SPLINE) spec.spline_seeds.push_back({n, A(n)});
         }
-        factor_spec(g, spec);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
     }

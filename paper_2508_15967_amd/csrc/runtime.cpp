@@ -381,13 +381,11 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     if (p->tune.empty()) tune_load(p);
     auto it = p->tune.find(key);
     if (it != p->tune.end()) { *out = it->second; p->last.tuned = 1; return RG_OK; }
+    // a shortened run of the real launch, stores included (they write the
+    // caller's first snapshots and checkpoints, which the run that follows
+    // overwrites): long enough to rank the candidates above timer noise
     rg_kargs t = a;
-    t.n_steps = std::min(a.n_steps, 128);  // long enough to rank the candidates above timer noise
-    t.store_every = 0;
-    t.traj = nullptr;
-    t.traj_D = nullptr;
-    t.ckpt_every = 0;
-    t.ckpt = nullptr;
+    t.n_steps = std::min(a.n_steps, std::max(128, std::min(1024, a.n_steps / 16)));
     float best = 1e30f;
     TuneEntry bt;
     for (int rpl : {1, 2})
