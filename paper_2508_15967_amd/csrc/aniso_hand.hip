@@ -16,7 +16,6 @@
 #include <string>
 
 #include "../../include/raygraph_hand.h"
-#include "kernels/rg_prelude.h"  // rg_exp: the same exponential as the compiled kernels
 
 namespace {
 
@@ -49,7 +48,7 @@ __device__ __forceinline__ void hand_rhs(const rg_hand_aniso &m, const double *s
         const double dx = y[0] - m.c[b][0], dy = y[1] - m.c[b][1], dz = y[2] - m.c[b][2];
         const double iw = m.inv_w2[b];
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const double sg = sv[b] * rg_exp(-r2 * iw);
+        const double sg = sv[b] * exp(-r2 * iw);
         const double *M = m.m[b];
         const double mk0 = fma(M[2], k2, fma(M[1], k1, M[0] * k0));
         const double mk1 = fma(M[4], k2, fma(M[3], k1, M[1] * k0));
@@ -79,7 +78,7 @@ __device__ __forceinline__ void hand_vjp(const rg_hand_aniso &m, const double *s
         const double dx = y[0] - m.c[b][0], dy = y[1] - m.c[b][1], dz = y[2] - m.c[b][2];
         const double iw = m.inv_w2[b];
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const double g = rg_exp(-r2 * iw);
+        const double g = exp(-r2 * iw);
         const double sg = sv[b] * g;
         const double *M = m.m[b];
         const double mk0 = fma(M[2], k2, fma(M[1], k1, M[0] * k0));
@@ -122,16 +121,8 @@ __device__ __forceinline__ void hand_step(const rg_hand_aniso &m, const double *
     for (int i = 0; i < 6; i++) { acc[i] = acc[i] + K[i]; yn[i] = fma(dt6, acc[i], y[i]); }
 }
 
-__constant__ double hand_exp_tab[64] = {RG_EXP_TABLE_VALUES};
-
-__device__ __forceinline__ void hand_stage_exp() {
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) rg_exp_lds[i] = hand_exp_tab[i];
-    __syncthreads();
-}
-
 template <int NB>
 __global__ void __launch_bounds__(512) hand_trace(rg_hand_aniso m, Args a) {
-    hand_stage_exp();
     const long long n = a.n;
     const long long G = (long long)gridDim.x * blockDim.x;
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += G) {
@@ -160,7 +151,6 @@ __global__ void __launch_bounds__(512) hand_trace(rg_hand_aniso m, Args a) {
 
 template <int NB>
 __global__ void __launch_bounds__(512) hand_adjoint(rg_hand_aniso m, Args a) {
-    hand_stage_exp();
     __shared__ double red[8][NB];
     const long long n = a.n, SL = a.lanes;
     const long long G = (long long)gridDim.x * blockDim.x;
