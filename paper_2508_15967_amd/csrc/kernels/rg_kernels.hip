@@ -126,8 +126,11 @@ __device__ __forceinline__ bool rg_outside(const rg_kargs &a, const T *y) {
 // into vector-register lanes).  The arithmetic is the same in both forms.
 #define RG_ZERO(i) ((RG_RHS_ZERO >> (i)) & 1u)
 
+// With st non-null (the adjoint's segment buffer) the stage states Y2, Y3,
+// Y4 are also stored, at st[(s RG_NY + c) SL] for stage s = 1..3.
 template <typename T>
-__device__ __forceinline__ void rg_rk4_step(const T *y, T om, T t, T dt, const rg_P &P, T *yn) {
+__device__ __forceinline__ void rg_rk4_step(const T *y, T om, T t, T dt, const rg_P &P, T *yn,
+                                            double *st = nullptr, long long SL = 0) {
     const T h2 = T(0.5) * dt, dt6 = dt / T(6.0);
     T K[RG_NY], acc[RG_NY], Y[RG_NY];
 #if RG_ROLL
@@ -143,18 +146,26 @@ __device__ __forceinline__ void rg_rk4_step(const T *y, T om, T t, T dt, const r
                 acc[i] = s == 0 ? K[i] : fma(T(2.0), K[i], acc[i]);
                 Y[i] = fma(c, K[i], y[i]);
             }
+        if (st)
+            for (int i = 0; i < RG_NY; i++) st[(long long)((s + 1) * RG_NY + i) * SL] = Y[i];
     }
 #else
     rg_rhs(y, om, t, P, K);
     for (int i = 0; i < RG_NY; i++) { acc[i] = K[i]; Y[i] = RG_ZERO(i) ? y[i] : fma(h2, K[i], y[i]); }
+    if (st)
+        for (int i = 0; i < RG_NY; i++) st[(long long)(RG_NY + i) * SL] = Y[i];
     rg_rhs(Y, om, t + h2, P, K);
     for (int i = 0; i < RG_NY; i++) {
         if (!RG_ZERO(i)) { acc[i] = fma(T(2.0), K[i], acc[i]); Y[i] = fma(h2, K[i], y[i]); }
     }
+    if (st)
+        for (int i = 0; i < RG_NY; i++) st[(long long)(2 * RG_NY + i) * SL] = Y[i];
     rg_rhs(Y, om, t + h2, P, K);
     for (int i = 0; i < RG_NY; i++) {
         if (!RG_ZERO(i)) { acc[i] = fma(T(2.0), K[i], acc[i]); Y[i] = fma(dt, K[i], y[i]); }
     }
+    if (st)
+        for (int i = 0; i < RG_NY; i++) st[(long long)(3 * RG_NY + i) * SL] = Y[i];
     rg_rhs(Y, om, t + dt, P, K);
 #endif
     for (int i = 0; i < RG_NY; i++) yn[i] = RG_ZERO(i) ? y[i] : fma(dt6, acc[i] + K[i], y[i]);
@@ -663,46 +674,35 @@ __shared__ double rg_red_lds[8 * RG_NGRAD1];
 // Segments between forward checkpoints are walked last to first; the states
 // of a segment are recomputed from its checkpoint into per-lane scratch
 // (coalesced [j][c][lane]) and read back in reverse.
-#if RG_ROLL
-// Reverse of one RK4 step with one copy of the right-hand side and one of
-// the VJP (see RG_ROLL above): the stage states Y2..Y4 wait in LDS (one
-// slot per lane and component), Y1 is re-read from the segment buffer.
-// Same arithmetic as the unrolled form.
-__shared__ double rg_stage_lds[3 * RG_NY * RG_ADJ_BLOCK];
-
-__device__ __forceinline__ void rg_adjoint_step_rolled(const double *sp, long long SL, double om,
-                                                       double dt, const rg_P &P, double *lam,
-                                                       double *gp, rg_GA &G) {
+// Reverse of one RK4 step from the four stage states stored by the
+// segment's forward recomputation (sp: stage s component c at
+// sp[(s RG_NY + c) SL], t at sp[4 RG_NY SL]): the discrete adjoint
+// recurrence with one VJP per stage, last stage first: a loop around one
+// copy of the VJP (four inlined copies cost registers and code and add no
+// parallelism, the stages depending on each other), the next stage's state
+// loaded before the current VJP runs.
+__device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, double om, double dt,
+                                                const rg_P &P, double *lam, double *gp, rg_GA &G) {
     const double h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
-    const int tid = threadIdx.x;
-    const double tj = sp[(long long)RG_NY * SL];
-    double Y[RG_NY], K[RG_NY];
-    for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)c * SL];
-#pragma unroll 1
-    for (int s = 0; s < 3; s++) {
-        rg_rhs(Y, om, s == 0 ? tj : tj + h2, P, K);
-        const double cs = s == 2 ? dt : h2;
-        for (int c = 0; c < RG_NY; c++) {
-            Y[c] = fma(cs, K[c], sp[(long long)c * SL]);
-            rg_stage_lds[(s * RG_NY + c) * RG_ADJ_BLOCK + tid] = Y[c];
-        }
-    }
-    double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY];
+    const double tj = sp[(long long)4 * RG_NY * SL];
+    double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY], Y[RG_NY];
     for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
+    for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)(3 * RG_NY + c) * SL];
 #pragma unroll 1
     for (int s = 3; s >= 0; s--) {
-        for (int c = 0; c < RG_NY; c++)
-            Y[c] = s == 0 ? sp[(long long)c * SL] : rg_stage_lds[((s - 1) * RG_NY + c) * RG_ADJ_BLOCK + tid];
+        double Yn[RG_NY];
+        const int sn = s > 0 ? s - 1 : 0;
+        for (int c = 0; c < RG_NY; c++) Yn[c] = sp[(long long)(sn * RG_NY + c) * SL];
         rg_vjp(Y, om, s == 0 ? tj : (s == 3 ? tj + dt : tj + h2), P, Kb, Yb, gp, G);
         const double ca = s == 3 ? dt : h2, cb = s == 1 ? dt6 : dt3;
         for (int c = 0; c < RG_NY; c++) {
             lsum[c] = s == 3 ? Yb[c] : lsum[c] + Yb[c];
             Kb[c] = fma(ca, Yb[c], cb * lam[c]);
+            Y[c] = Yn[c];
         }
     }
     for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + lsum[c];
 }
-#endif
 
 extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kargs a) {
     rg_stage_tables(a);
@@ -718,7 +718,7 @@ extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kar
     const long long n = a.n;
     const long long GL = (long long)gridDim.x * blockDim.x;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const double dt = a.dt, h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
+    const double dt = a.dt;
     const int ce = a.ckpt_every;
     const long long SL = a.scratch_lanes;
     for (long long rid = gid; rid < a.n_run; rid += GL) {
@@ -739,40 +739,17 @@ extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kar
             for (int c = 0; c < RG_NY; c++) y[c] = cp[(long long)c * n];
             t = cp[(long long)RG_NY * n];
             for (int j = s0; j < s1; j++) {
-                double *sp = a.scratch + (long long)(j - s0) * (RG_NY + 1) * SL + gid;
+                double *sp = a.scratch + (long long)(j - s0) * (4 * RG_NY + 1) * SL + gid;
                 for (int c = 0; c < RG_NY; c++) sp[(long long)c * SL] = y[c];
-                sp[(long long)RG_NY * SL] = t;
+                sp[(long long)4 * RG_NY * SL] = t;
                 double yn[RG_NY];
-                rg_rk4_step(y, om, t, dt, P, yn);
+                rg_rk4_step(y, om, t, dt, P, yn, sp, SL);
                 for (int c = 0; c < RG_NY; c++) y[c] = yn[c];
                 t = t + dt;
             }
-            for (int j = s1 - 1; j >= s0; j--) {
-                const double *sp = a.scratch + (long long)(j - s0) * (RG_NY + 1) * SL + gid;
-#if RG_ROLL
-                rg_adjoint_step_rolled(sp, SL, om, dt, P, lam, gp, G);
-#else
-                double Y1[RG_NY], Y2[RG_NY], Y3[RG_NY], Y4[RG_NY], K[RG_NY];
-                for (int c = 0; c < RG_NY; c++) Y1[c] = sp[(long long)c * SL];
-                const double tj = sp[(long long)RG_NY * SL];
-                rg_rhs(Y1, om, tj, P, K);
-                for (int c = 0; c < RG_NY; c++) Y2[c] = fma(h2, K[c], Y1[c]);
-                rg_rhs(Y2, om, tj + h2, P, K);
-                for (int c = 0; c < RG_NY; c++) Y3[c] = fma(h2, K[c], Y1[c]);
-                rg_rhs(Y3, om, tj + h2, P, K);
-                for (int c = 0; c < RG_NY; c++) Y4[c] = fma(dt, K[c], Y1[c]);
-                double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY];
-                for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
-                rg_vjp(Y4, om, tj + dt, P, Kb, Yb, gp, G);
-                for (int c = 0; c < RG_NY; c++) { lsum[c] = Yb[c]; Kb[c] = fma(dt, Yb[c], dt3 * lam[c]); }
-                rg_vjp(Y3, om, tj + h2, P, Kb, Yb, gp, G);
-                for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt3 * lam[c]); }
-                rg_vjp(Y2, om, tj + h2, P, Kb, Yb, gp, G);
-                for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt6 * lam[c]); }
-                rg_vjp(Y1, om, tj, P, Kb, Yb, gp, G);
-                for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + (lsum[c] + Yb[c]);
-#endif
-            }
+            for (int j = s1 - 1; j >= s0; j--)
+                rg_adjoint_step(a.scratch + (long long)(j - s0) * (4 * RG_NY + 1) * SL + gid, SL, om, dt, P,
+                                lam, gp, G);
         }
         for (int i = 0; i < RG_DIM; i++) {
             if (a.gx0) a.gx0[i * n + rid] = lam[i];

@@ -264,12 +264,12 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     if (p->has_vjp) {
         I.vjp_flops_alg = fl_vjp.alg;
         I.vjp_flops_issued = fl_vjp.issued;
-        // reverse of one step: recompute (one RK4 step) + 3 stage RHS + 4 VJP
-        // + stage states (3 fma) + recurrence (per component: 3 fma, 3 add,
-        // 1 mul, 1 add = 12 flops)
-        const double rec = (3 * 2 + 12) * ny;
-        I.adj_step_flops_alg = I.rk4_step_flops_alg + 3 * fl_rhs.alg + 4 * fl_vjp.alg + rec;
-        I.adj_step_flops_issued = I.rk4_step_flops_issued + 3 * fl_rhs.issued + 4 * fl_vjp.issued + rec;
+        // reverse of one step: recompute (one RK4 step, its stage states
+        // stored) + 4 VJP + recurrence (per component: 3 fma, 3 add, 1 mul,
+        // 1 add = 12 flops)
+        const double rec = 12.0 * ny;
+        I.adj_step_flops_alg = I.rk4_step_flops_alg + 4 * fl_vjp.alg + rec;
+        I.adj_step_flops_issued = I.rk4_step_flops_issued + 4 * fl_vjp.issued + rec;
     }
 
     // ---- full source: one self-contained translation unit (headers spliced
