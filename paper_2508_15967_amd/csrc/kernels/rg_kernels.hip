@@ -674,25 +674,55 @@ __shared__ double rg_red_lds[8 * RG_NGRAD1];
 // Segments between forward checkpoints are walked last to first; the states
 // of a segment are recomputed from its checkpoint into per-lane scratch
 // (coalesced [j][c][lane]) and read back in reverse.
-// Reverse of one RK4 step from the four stage states stored by the
-// segment's forward recomputation (sp: stage s component c at
-// sp[(s RG_NY + c) SL], t at sp[4 RG_NY SL]): the discrete adjoint
-// recurrence with one VJP per stage, last stage first: a loop around one
-// copy of the VJP (four inlined copies cost registers and code and add no
-// parallelism, the stages depending on each other), the next stage's state
-// loaded before the current VJP runs.
+// Reverse of one RK4 step: the discrete adjoint recurrence with one VJP
+// per stage, last stage first, as a loop around one copy of the VJP (four
+// inlined copies cost registers and code and add no parallelism, the
+// stages depending on each other).  The stage states come from the
+// segment buffer sp (stage s component c at sp[(s RG_NY + c) SL], t at
+// sp[RG_ADJ_NS RG_NY SL]): with RG_ADJ_RECOMPUTE only Y1 is stored and
+// Y2..Y4 are recomputed here (three right-hand sides, the states waiting
+// in LDS), which pays where the right-hand side is cheap next to a global
+// load; otherwise the segment's forward recomputation stored all four and
+// the next stage's state is loaded before the current VJP runs.
+#if RG_ADJ_RECOMPUTE
+#define RG_ADJ_NS 1
+__shared__ double rg_stage_lds[3 * RG_NY * RG_ADJ_BLOCK];
+#else
+#define RG_ADJ_NS 4
+#endif
+
 __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, double om, double dt,
                                                 const rg_P &P, double *lam, double *gp, rg_GA &G) {
     const double h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
-    const double tj = sp[(long long)4 * RG_NY * SL];
+    const double tj = sp[(long long)RG_ADJ_NS * RG_NY * SL];
     double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY], Y[RG_NY];
-    for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
+#if RG_ADJ_RECOMPUTE
+    const int tid = threadIdx.x;
+    for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)c * SL];
+#pragma unroll 1
+    for (int s = 0; s < 3; s++) {
+        double K[RG_NY];
+        rg_rhs(Y, om, s == 0 ? tj : tj + h2, P, K);
+        const double cs = s == 2 ? dt : h2;
+        for (int c = 0; c < RG_NY; c++) {
+            Y[c] = fma(cs, K[c], sp[(long long)c * SL]);
+            rg_stage_lds[(s * RG_NY + c) * RG_ADJ_BLOCK + tid] = Y[c];
+        }
+    }
+#else
     for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)(3 * RG_NY + c) * SL];
+#endif
+    for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
 #pragma unroll 1
     for (int s = 3; s >= 0; s--) {
         double Yn[RG_NY];
         const int sn = s > 0 ? s - 1 : 0;
+#if RG_ADJ_RECOMPUTE
+        for (int c = 0; c < RG_NY; c++)
+            Yn[c] = sn == 0 ? sp[(long long)c * SL] : rg_stage_lds[((sn - 1) * RG_NY + c) * RG_ADJ_BLOCK + tid];
+#else
         for (int c = 0; c < RG_NY; c++) Yn[c] = sp[(long long)(sn * RG_NY + c) * SL];
+#endif
         rg_vjp(Y, om, s == 0 ? tj : (s == 3 ? tj + dt : tj + h2), P, Kb, Yb, gp, G);
         const double ca = s == 3 ? dt : h2, cb = s == 1 ? dt6 : dt3;
         for (int c = 0; c < RG_NY; c++) {
@@ -739,17 +769,17 @@ extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kar
             for (int c = 0; c < RG_NY; c++) y[c] = cp[(long long)c * n];
             t = cp[(long long)RG_NY * n];
             for (int j = s0; j < s1; j++) {
-                double *sp = a.scratch + (long long)(j - s0) * (4 * RG_NY + 1) * SL + gid;
+                double *sp = a.scratch + (long long)(j - s0) * (RG_ADJ_NS * RG_NY + 1) * SL + gid;
                 for (int c = 0; c < RG_NY; c++) sp[(long long)c * SL] = y[c];
-                sp[(long long)4 * RG_NY * SL] = t;
+                sp[(long long)RG_ADJ_NS * RG_NY * SL] = t;
                 double yn[RG_NY];
-                rg_rk4_step(y, om, t, dt, P, yn, sp, SL);
+                rg_rk4_step(y, om, t, dt, P, yn, RG_ADJ_NS > 1 ? sp : nullptr, SL);
                 for (int c = 0; c < RG_NY; c++) y[c] = yn[c];
                 t = t + dt;
             }
             for (int j = s1 - 1; j >= s0; j--)
-                rg_adjoint_step(a.scratch + (long long)(j - s0) * (4 * RG_NY + 1) * SL + gid, SL, om, dt, P,
-                                lam, gp, G);
+                rg_adjoint_step(a.scratch + (long long)(j - s0) * (RG_ADJ_NS * RG_NY + 1) * SL + gid, SL, om,
+                                dt, P, lam, gp, G);
         }
         for (int i = 0; i < RG_DIM; i++) {
             if (a.gx0) a.gx0[i * n + rid] = lam[i];

@@ -223,6 +223,11 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         p->info.n_nodes_vjp = fl_vjp.ops;
     }
     p->functions_src = fs.str();
+    // The adjoint recomputes the stage states Y2..Y4 where three right-hand
+    // sides cost less than waiting for them from the segment buffer (a few
+    // hundred issued flops against a global-memory latency the few waves of
+    // a small ray batch cannot hide); otherwise they are stored.
+    p->adj_recompute = fl_rhs.issued < 400.0;
 
     // ---- configuration header
     std::ostringstream cs;
@@ -232,7 +237,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
        << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_HAS_F32 " << (p->has_f32 ? 1 : 0)
        << "\n#define RG_USES_EXP " << (p->functions_src.find("rg_exp(") != std::string::npos ? 1 : 0)
        << "\n#define RG_RHS_ZERO " << zero_mask
-       << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_BLOCK " << kAdjointBlock
+       << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_RECOMPUTE "
+       << (p->adj_recompute ? 1 : 0) << "\n#define RG_ADJ_BLOCK " << kAdjointBlock
        << "\n";
     cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)
        << int_array("rg_spl_len", p->spl_len) << int_array("rg_spl_ny", p->spl_ny)
@@ -264,12 +270,14 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     if (p->has_vjp) {
         I.vjp_flops_alg = fl_vjp.alg;
         I.vjp_flops_issued = fl_vjp.issued;
-        // reverse of one step: recompute (one RK4 step, its stage states
-        // stored) + 4 VJP + recurrence (per component: 3 fma, 3 add, 1 mul,
-        // 1 add = 12 flops)
+        // reverse of one step: recompute (one RK4 step) [+ 3 stage RHS and
+        // 3 stage fma when the stages are recomputed] + 4 VJP + recurrence
+        // (per component: 3 fma, 3 add, 1 mul, 1 add = 12 flops)
         const double rec = 12.0 * ny;
-        I.adj_step_flops_alg = I.rk4_step_flops_alg + 4 * fl_vjp.alg + rec;
-        I.adj_step_flops_issued = I.rk4_step_flops_issued + 4 * fl_vjp.issued + rec;
+        const double st_alg = p->adj_recompute ? 3 * fl_rhs.alg + 6.0 * ny : 0.0;
+        const double st_iss = p->adj_recompute ? 3 * fl_rhs.issued + 6.0 * ny : 0.0;
+        I.adj_step_flops_alg = I.rk4_step_flops_alg + st_alg + 4 * fl_vjp.alg + rec;
+        I.adj_step_flops_issued = I.rk4_step_flops_issued + st_iss + 4 * fl_vjp.issued + rec;
     }
 
     // ---- full source: one self-contained translation unit (headers spliced

@@ -36,6 +36,7 @@ struct rg_program {
     bool compile_only = false;
     bool rolled = false;  // RK4 stage loops rolled (RG_ROLL)
     bool has_f32 = false; // single precision RK4 kernel built (RG_HAS_F32)
+    bool adj_recompute = false;  // adjoint recomputes stage states (RG_ADJ_RECOMPUTE)
     // gradient layout
     std::vector<int> grad_param, grad_elem;       // scalar slots
     std::vector<int> spl_param, spl_off, spl_len, spl_ny;

@@ -579,8 +579,8 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     RGCHK(occupancy_grid(p, "rg_rk4_adjoint", block, (long long)cdiv(n, block), &grid));
     const long long lanes = (long long)grid * block;
     const int stride = (int)(p->grad_param.size() + (size_t)p->spl_total);
-    // per lane and step of a segment: the four RK4 stage states and t
-    const size_t scratch = (size_t)d.checkpoint_every * (4 * ny + 1) * lanes;
+    // per lane and step of a segment: the RK4 stage states kept (1 or 4) and t
+    const size_t scratch = (size_t)d.checkpoint_every * ((p->adj_recompute ? 1 : 4) * ny + 1) * lanes;
     const size_t gpart = (size_t)grid * stride;
     RGCHK(ensure_ws(p, 8 * (scratch + gpart) + 1024));
     Carve c{(char *)p->ws};
