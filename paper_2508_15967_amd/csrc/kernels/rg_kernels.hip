@@ -675,18 +675,22 @@ __shared__ double rg_red_lds[8 * RG_NGRAD1];
 // of a segment are recomputed from its checkpoint into per-lane scratch
 // (coalesced [j][c][lane]) and read back in reverse.
 // Reverse of one RK4 step: the discrete adjoint recurrence with one VJP
-// per stage, last stage first, as a loop around one copy of the VJP (four
-// inlined copies cost registers and code and add no parallelism, the
-// stages depending on each other).  The stage states come from the
-// segment buffer sp (stage s component c at sp[(s RG_NY + c) SL], t at
-// sp[RG_ADJ_NS RG_NY SL]): with RG_ADJ_RECOMPUTE only Y1 is stored and
-// Y2..Y4 are recomputed here (three right-hand sides, the states waiting
-// in LDS), which pays where the right-hand side is cheap next to a global
-// load; otherwise the segment's forward recomputation stored all four and
-// the next stage's state is loaded before the current VJP runs.
+// per stage, last stage first.  The stage states come from the segment
+// buffer sp (stage s component c at sp[(s RG_NY + c) SL], t at
+// sp[RG_ADJ_NS RG_NY SL]).
+//
+// RG_ADJ_RECOMPUTE (a cheap right-hand side): only Y1 is stored; Y2..Y4 are
+// recomputed here with three right-hand sides and kept in registers, the
+// four VJPs inlined.  Otherwise the segment's forward recomputation stored
+// all four states and the stages are a loop around one copy of the VJP
+// (four inlined copies of a large VJP cost registers and code and add no
+// parallelism, the stages depending on each other), the next stage's state
+// loaded before the current VJP runs.  (Measured on the spline workload,
+// one wave per SIMD: inlined recomputation 23.6 ms, looped recomputation
+// with LDS 27.2 ms, stored states 28.3 ms; on the anisotropic workload the
+// stored states are 13 % faster than the recomputation.)
 #if RG_ADJ_RECOMPUTE
 #define RG_ADJ_NS 1
-__shared__ double rg_stage_lds[3 * RG_NY * RG_ADJ_BLOCK];
 #else
 #define RG_ADJ_NS 4
 #endif
@@ -695,34 +699,34 @@ __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, 
                                                 const rg_P &P, double *lam, double *gp, rg_GA &G) {
     const double h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
     const double tj = sp[(long long)RG_ADJ_NS * RG_NY * SL];
-    double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY], Y[RG_NY];
+    double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY];
 #if RG_ADJ_RECOMPUTE
-    const int tid = threadIdx.x;
-    for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)c * SL];
-#pragma unroll 1
-    for (int s = 0; s < 3; s++) {
-        double K[RG_NY];
-        rg_rhs(Y, om, s == 0 ? tj : tj + h2, P, K);
-        const double cs = s == 2 ? dt : h2;
-        for (int c = 0; c < RG_NY; c++) {
-            Y[c] = fma(cs, K[c], sp[(long long)c * SL]);
-            rg_stage_lds[(s * RG_NY + c) * RG_ADJ_BLOCK + tid] = Y[c];
-        }
-    }
+    double Y1[RG_NY], Y2[RG_NY], Y3[RG_NY], Y4[RG_NY], K[RG_NY];
+    for (int c = 0; c < RG_NY; c++) Y1[c] = sp[(long long)c * SL];
+    rg_rhs(Y1, om, tj, P, K);
+    for (int c = 0; c < RG_NY; c++) Y2[c] = fma(h2, K[c], Y1[c]);
+    rg_rhs(Y2, om, tj + h2, P, K);
+    for (int c = 0; c < RG_NY; c++) Y3[c] = fma(h2, K[c], Y1[c]);
+    rg_rhs(Y3, om, tj + h2, P, K);
+    for (int c = 0; c < RG_NY; c++) Y4[c] = fma(dt, K[c], Y1[c]);
+    for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
+    rg_vjp(Y4, om, tj + dt, P, Kb, Yb, gp, G);
+    for (int c = 0; c < RG_NY; c++) { lsum[c] = Yb[c]; Kb[c] = fma(dt, Yb[c], dt3 * lam[c]); }
+    rg_vjp(Y3, om, tj + h2, P, Kb, Yb, gp, G);
+    for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt3 * lam[c]); }
+    rg_vjp(Y2, om, tj + h2, P, Kb, Yb, gp, G);
+    for (int c = 0; c < RG_NY; c++) { lsum[c] += Yb[c]; Kb[c] = fma(h2, Yb[c], dt6 * lam[c]); }
+    rg_vjp(Y1, om, tj, P, Kb, Yb, gp, G);
+    for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + (lsum[c] + Yb[c]);
 #else
+    double Y[RG_NY];
     for (int c = 0; c < RG_NY; c++) Y[c] = sp[(long long)(3 * RG_NY + c) * SL];
-#endif
     for (int c = 0; c < RG_NY; c++) Kb[c] = dt6 * lam[c];
 #pragma unroll 1
     for (int s = 3; s >= 0; s--) {
         double Yn[RG_NY];
         const int sn = s > 0 ? s - 1 : 0;
-#if RG_ADJ_RECOMPUTE
-        for (int c = 0; c < RG_NY; c++)
-            Yn[c] = sn == 0 ? sp[(long long)c * SL] : rg_stage_lds[((sn - 1) * RG_NY + c) * RG_ADJ_BLOCK + tid];
-#else
         for (int c = 0; c < RG_NY; c++) Yn[c] = sp[(long long)(sn * RG_NY + c) * SL];
-#endif
         rg_vjp(Y, om, s == 0 ? tj : (s == 3 ? tj + dt : tj + h2), P, Kb, Yb, gp, G);
         const double ca = s == 3 ? dt : h2, cb = s == 1 ? dt6 : dt3;
         for (int c = 0; c < RG_NY; c++) {
@@ -732,6 +736,7 @@ __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, 
         }
     }
     for (int c = 0; c < RG_NY; c++) lam[c] = lam[c] + lsum[c];
+#endif
 }
 
 extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kargs a) {
