@@ -612,11 +612,24 @@ std::vector<uint32_t> Graph::factor_sums(const std::vector<uint32_t> &roots) {
         if (is_sum(n)) {
             if (sum_of[n] < 0) continue;  // folded into its consumers
             const Sum &S = sums[sum_of[n]];
-            uint32_t acc = NONE;
+            // equal terms are combined first: m x is one scaled term (an fma
+            // in an accumulation) instead of m additions
+            std::map<uint64_t, long> mult;
+            std::vector<uint64_t> ids;
             for (uint64_t s2 : S.sym) {
-                const uint32_t t = get_abs(s2);
-                if (acc == NONE) acc = neg_of(s2) ? neg(t) : t;
-                else acc = neg_of(s2) ? sub(acc, t) : add(acc, t);
+                const uint64_t id = id_of(s2);
+                if (!mult.count(id)) ids.push_back(id);
+                mult[id] += neg_of(s2) ? -1 : 1;
+            }
+            uint32_t acc = NONE;
+            for (uint64_t id : ids) {
+                const long m = mult[id];
+                if (m == 0) continue;
+                uint32_t t = get_abs(id << 1);
+                const bool ng = m < 0;
+                if (m != 1 && m != -1) t = mul(constant((double)(ng ? -m : m)), t);
+                if (acc == NONE) acc = ng ? neg(t) : t;
+                else acc = ng ? sub(acc, t) : add(acc, t);
             }
             if (S.c != 0.0) acc = acc == NONE ? constant(S.c) : add(constant(S.c), acc);
             nw[n] = acc == NONE ? constant(0.0) : acc;
