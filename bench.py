@@ -303,8 +303,24 @@ def main():
         psteps = int(outs["steps_out"].cpu().numpy().astype(np.int64).sum())
         result["plain"] = {"value": psteps / pw, "ms_per_trace": pw * 1e3,
                            "launches_per_trace": w.n_steps + 2 if w.integrator == W.RK4 else None}
-        # forward against forward (the plain form has no adjoint)
+        # forward against forward
         result["speedup_vs_plain"] = (pw * 1e3 / psteps) / (fwd_ms / ray_steps)
+        if adjoint:
+            # the adjoint in its per-step form on the plain forward's checkpoints
+            def plain_bwd():
+                torch.mul(outs["x_out"] - adj["tx"], 2.0, out=adj["lx"])
+                prog.adjoint_desc(pdesc, adj["lx"], None, adj["gx0"], adj["gk0"], adj["gp"], stream)
+            plain_bwd()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.plain_steps):
+                plain_bwd()
+            torch.cuda.synchronize()
+            pb = (time.perf_counter() - t0) / args.plain_steps
+            result["plain"]["adj_ms"] = pb * 1e3
+            result["plain"]["fwd_adj_value"] = psteps / (pw + pb)
+            result["plain"]["adj_launches"] = 2 * w.n_steps + 2 * ((w.n_steps + w.ckpt_every - 1) // w.ckpt_every) + 3
+            result["speedup_vs_plain_fwd_adj"] = (pw + pb) * 1e3 / (fwd_ms + bwd_ms)
 
     # CPU oracle on a bounded sample of the same workload: a pilot run sizes
     # the sample to about --cpu-seconds of work on all host cores

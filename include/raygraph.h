@@ -268,7 +268,11 @@ typedef struct {
  * reverse sweep segment by segment from the forward checkpoints with the
  * states of each segment recomputed.  Gradients of a loss L whose
  * derivatives at the endpoints are given.  Workgroups hold
- * min(fwd->block, 256) threads (256 when fwd->block is 0). */
+ * min(fwd->block, 256) threads (256 when fwd->block is 0).  With
+ * fwd->mode == RG_PLAIN the same adjoint runs as one launch per step (the
+ * per-step comparator: state and adjoint pass through device memory
+ * between launches); results as the persistent form (per-ray gradients
+ * bitwise, parameter gradients up to the summation order). */
 rg_status rg_trace_rays_adjoint(rg_program *p, const rg_adjoint_desc *d, void *hip_stream);
 
 /* Elementwise evaluation of D and the right-hand side at n points (one

@@ -22,6 +22,8 @@ struct rg_kargs {
     double *dparams[RG_KMAX_PARAMS];
     // plain-mode state (SoA over rays) and counters
     double *s_y, *s_k1, *s_t, *s_h, *s_fm;
+    double *s_lam;            // plain adjoint: [NY][n]
+    int seg_s0;               // plain adjoint: first step of the segment
     int *s_st, *s_acc, *s_att;
     unsigned long long *queue;
     int *counter;

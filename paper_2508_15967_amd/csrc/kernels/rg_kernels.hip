@@ -739,6 +739,35 @@ __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, 
 #endif
 }
 
+// Parameter-gradient partials of this workgroup: the scalar slots reduced
+// in a fixed order (wave shuffles, then waves in order), the spline
+// coefficients from the LDS accumulator; written (add = false) or added to
+// what the workgroup's earlier launches left (add = true).
+__device__ __forceinline__ void rg_write_partials(const rg_kargs &a, const double *gp, rg_GA &G, bool add) {
+#if RG_NSPLTAB > 0
+    for (int k = 0; k < RG_NSPLTAB; k++) G.flush(k);
+#endif
+    (void)G;
+    if (!a.gpart) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int s = 0; s < RG_NGRAD; s++) {
+        double v = gp[s];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) rg_red_lds[wave * RG_NGRAD1 + s] = v;
+    }
+    __syncthreads();
+    double *out = a.gpart + (long long)blockIdx.x * a.part_stride;
+    for (int s = threadIdx.x; s < RG_NGRAD; s += blockDim.x) {
+        double v = 0.0;
+        for (int w = 0; w < nw; w++) v += rg_red_lds[w * RG_NGRAD1 + s];
+        out[s] = add ? out[s] + v : v;
+    }
+#if RG_NSPLTAB > 0
+    for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x)
+        out[RG_NGRAD + i] = add ? out[RG_NGRAD + i] + rg_spl_grad_lds[i] : rg_spl_grad_lds[i];
+#endif
+}
+
 extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kargs a) {
     rg_stage_tables(a);
 #if RG_NSPLTAB > 0
@@ -791,27 +820,80 @@ extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kar
             if (a.gk0) a.gk0[i * n + rid] = lam[RG_DIM + i];
         }
     }
-    // parameter-gradient partials of this workgroup (fixed-order for scalars)
+    rg_write_partials(a, gp, G, false);
+}
+
+// ------------------------------------------------------- plain adjoint --
+// One launch per step, state and adjoint in HBM between launches (the
+// per-step form of the same checkpointed adjoint): per segment, a launch
+// loads the checkpoint, one launch per step recomputes the state and
+// stores the stage states (segment buffer [j][RG_ADJ_NS NY + 1][n]), and
+// one launch per step runs the reverse step, its workgroup adding its
+// gradient partials to its own slot.  Rays stopped before a step skip it.
+extern "C" __global__ void __launch_bounds__(512) rg_adjp_init(rg_kargs a) {
+    const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.gpart)  // this workgroup's slot (same grid as rg_adjp_rev)
+        for (int s = threadIdx.x; s < a.part_stride; s += blockDim.x)
+            a.gpart[(long long)blockIdx.x * a.part_stride + s] = 0.0;
+    if (r >= a.n_run) return;
+    for (int i = 0; i < RG_DIM; i++) {
+        a.s_lam[i * n + r] = a.lam_x[i * n + r];
+        a.s_lam[(RG_DIM + i) * n + r] = a.lam_k ? a.lam_k[i * n + r] : 0.0;
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_adjp_seg(rg_kargs a) {
+    const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run) return;
+    const double *cp = a.ckpt + (long long)a.ckpt_idx * (RG_NY + 1) * n + r;
+    for (int c = 0; c < RG_NY; c++) a.s_y[c * n + r] = cp[(long long)c * n];
+    a.s_t[r] = cp[(long long)RG_NY * n];
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_adjp_fwd(rg_kargs a) {
+    rg_stage_tables(a);
+    const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run || a.step >= a.steps_out[r]) return;
+    const rg_P P = rg_params(a);
+    double y[RG_NY], yn[RG_NY];
+    for (int c = 0; c < RG_NY; c++) y[c] = a.s_y[c * n + r];
+    const double t = a.s_t[r];
+    double *sp = a.scratch + (long long)(a.step - a.seg_s0) * (RG_ADJ_NS * RG_NY + 1) * n + r;
+    for (int c = 0; c < RG_NY; c++) sp[(long long)c * n] = y[c];
+    sp[(long long)RG_ADJ_NS * RG_NY * n] = t;
+    rg_rk4_step(y, a.omega[r], t, a.dt, P, yn, RG_ADJ_NS > 1 ? sp : nullptr, n);
+    for (int c = 0; c < RG_NY; c++) a.s_y[c * n + r] = yn[c];
+    a.s_t[r] = t + a.dt;
+}
+
+extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_adjp_rev(rg_kargs a) {
+    rg_stage_tables(a);
 #if RG_NSPLTAB > 0
-    for (int k = 0; k < RG_NSPLTAB; k++) G.flush(k);
+    for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) rg_spl_grad_lds[i] = 0.0;
+    __syncthreads();
 #endif
-    if (a.gpart) {
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-        for (int s = 0; s < RG_NGRAD; s++) {
-            double v = gp[s];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (lane == 0) rg_red_lds[wave * RG_NGRAD1 + s] = v;
-        }
-        __syncthreads();
-        double *out = a.gpart + (long long)blockIdx.x * a.part_stride;
-        for (int s = threadIdx.x; s < RG_NGRAD; s += blockDim.x) {
-            double v = 0.0;
-            for (int w = 0; w < nw; w++) v += rg_red_lds[w * RG_NGRAD1 + s];
-            out[s] = v;
-        }
-#if RG_NSPLTAB > 0
-        for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) out[RG_NGRAD + i] = rg_spl_grad_lds[i];
-#endif
+    const rg_P P = rg_params(a);
+    rg_GA G;
+    G.init();
+    double gp[RG_NGRAD1];
+    for (int i = 0; i < RG_NGRAD1; i++) gp[i] = 0.0;
+    const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < a.n_run && a.step < a.steps_out[r]) {
+        double lam[RG_NY];
+        for (int c = 0; c < RG_NY; c++) lam[c] = a.s_lam[c * n + r];
+        rg_adjoint_step(a.scratch + (long long)(a.step - a.seg_s0) * (RG_ADJ_NS * RG_NY + 1) * n + r, n,
+                        a.omega[r], a.dt, P, lam, gp, G);
+        for (int c = 0; c < RG_NY; c++) a.s_lam[c * n + r] = lam[c];
+    }
+    rg_write_partials(a, gp, G, true);
+}
+
+extern "C" __global__ void __launch_bounds__(512) rg_adjp_finish(rg_kargs a) {
+    const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_run) return;
+    for (int i = 0; i < RG_DIM; i++) {
+        if (a.gx0) a.gx0[i * n + r] = a.s_lam[i * n + r];
+        if (a.gk0) a.gk0[i * n + r] = a.s_lam[(RG_DIM + i) * n + r];
     }
 }
 

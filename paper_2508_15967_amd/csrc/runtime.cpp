@@ -31,7 +31,8 @@ namespace rg {
 static const char *const KERNELS[] = {
     "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
     "rg_dopri_persistent", "rg_dopri_plain_init", "rg_dopri_plain_step", "rg_fill_f64",
-    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k", "rg_rk4_f32"};
+    "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k", "rg_rk4_f32",
+    "rg_adjp_init", "rg_adjp_seg", "rg_adjp_fwd", "rg_adjp_rev", "rg_adjp_finish"};
 
 static void drop_graphs(rg_program *p) {
     for (GraphEntry &ge : p->graphs) {
@@ -575,21 +576,8 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     a.gk0 = ad.dL_dk0;
 
     const int block = d.block > 0 && d.block < kAdjointBlock ? d.block : kAdjointBlock;
-    unsigned grid;
-    RGCHK(occupancy_grid(p, "rg_rk4_adjoint", block, (long long)cdiv(n, block), &grid));
-    const long long lanes = (long long)grid * block;
     const int stride = (int)(p->grad_param.size() + (size_t)p->spl_total);
-    // per lane and step of a segment: the RK4 stage states kept (1 or 4) and t
-    const size_t scratch = (size_t)d.checkpoint_every * ((p->adj_recompute ? 1 : 4) * ny + 1) * lanes;
-    const size_t gpart = (size_t)grid * stride;
-    RGCHK(ensure_ws(p, 8 * (scratch + gpart) + 1024));
-    Carve c{(char *)p->ws};
-    a.scratch = c.take<double>(scratch);
-    a.gpart = stride > 0 ? c.take<double>(gpart) : nullptr;
-    a.scratch_lanes = lanes;
-    a.n_part = (int)grid;
-    a.part_stride = stride;
-
+    const int ns_kept = p->adj_recompute ? 1 : 4;  // stage states per step in the segment buffer
     // zero the parameter gradients that will be written
     for (uint32_t i = 0; i < p->n_params; i++)
         if (a.dparams[i]) {
@@ -600,6 +588,61 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
             f.fill_v = 0.0;
             RGCHK(launch_one(p, Launch{"rg_fill_f64", cdiv(f.fill_n, 256), 256, f}, s));
         }
+
+    if (d.mode == RG_PLAIN) {
+        // one launch per step, per-ray state and adjoint in the workspace
+        const unsigned grid = cdiv(n, block);
+        const size_t seg = (size_t)d.checkpoint_every * (ns_kept * ny + 1) * n;
+        const size_t gpart = (size_t)grid * stride;
+        RGCHK(ensure_ws(p, 8 * (seg + 2 * ny * (size_t)n + (size_t)n + gpart) + 1024));
+        Carve c{(char *)p->ws};
+        a.scratch = c.take<double>(seg);
+        a.s_y = c.take<double>(ny * n);
+        a.s_lam = c.take<double>(ny * n);
+        a.s_t = c.take<double>(n);
+        a.gpart = stride > 0 ? c.take<double>(gpart) : nullptr;
+        a.n_part = (int)grid;
+        a.part_stride = stride;
+        std::vector<Launch> seq;
+        seq.push_back(Launch{"rg_adjp_init", grid, (unsigned)block, a});
+        const int ce = d.checkpoint_every;
+        const int nseg = (d.n_steps + ce - 1) / ce;
+        for (int sg = nseg - 1; sg >= 0; sg--) {
+            const int s0 = sg * ce, s1 = std::min(s0 + ce, d.n_steps);
+            rg_kargs b = a;
+            b.ckpt_idx = sg;
+            b.seg_s0 = s0;
+            seq.push_back(Launch{"rg_adjp_seg", grid, (unsigned)block, b});
+            for (int j = s0; j < s1; j++) {
+                b.step = j;
+                seq.push_back(Launch{"rg_adjp_fwd", grid, (unsigned)block, b});
+            }
+            for (int j = s1 - 1; j >= s0; j--) {
+                b.step = j;
+                seq.push_back(Launch{"rg_adjp_rev", grid, (unsigned)block, b});
+            }
+        }
+        seq.push_back(Launch{"rg_adjp_finish", grid, (unsigned)block, a});
+        if (stride > 0) seq.push_back(Launch{"rg_grad_finalize", cdiv(stride, 256), 256, a});
+        RGCHK(run_seq(p, seq, false, s));
+        p->last.block = block;
+        p->last.grid = (int)grid;
+        return RG_OK;
+    }
+
+    unsigned grid;
+    RGCHK(occupancy_grid(p, "rg_rk4_adjoint", block, (long long)cdiv(n, block), &grid));
+    const long long lanes = (long long)grid * block;
+    // per lane and step of a segment: the RK4 stage states kept (1 or 4) and t
+    const size_t scratch = (size_t)d.checkpoint_every * (ns_kept * ny + 1) * lanes;
+    const size_t gpart = (size_t)grid * stride;
+    RGCHK(ensure_ws(p, 8 * (scratch + gpart) + 1024));
+    Carve c{(char *)p->ws};
+    a.scratch = c.take<double>(scratch);
+    a.gpart = stride > 0 ? c.take<double>(gpart) : nullptr;
+    a.scratch_lanes = lanes;
+    a.n_part = (int)grid;
+    a.part_stride = stride;
     RGCHK(launch_one(p, Launch{"rg_rk4_adjoint", grid, (unsigned)block, a}, s));
     if (stride > 0) RGCHK(launch_one(p, Launch{"rg_grad_finalize", cdiv(stride, 256), 256, a}, s));
     p->last.block = block;

@@ -104,6 +104,19 @@ class Workload:
     def n(self) -> int:
         return int(self.x0.shape[1])
 
+    def select(self, idx) -> "Workload":
+        """The rays ``idx`` of this workload (same medium and settings)."""
+        idx = np.asarray(idx)
+        w = dataclasses.replace(self)
+        w.x0 = np.ascontiguousarray(self.x0[:, idx])
+        w.k0 = np.ascontiguousarray(self.k0[:, idx])
+        w.omega = np.ascontiguousarray(self.omega[idx])
+        if self.budget is not None:
+            w.budget = np.ascontiguousarray(self.budget[idx])
+        if self.targets is not None:
+            w.targets = np.ascontiguousarray(self.targets[:, idx])
+        return w
+
     def subset(self, n: int) -> "Workload":
         """First ``n`` rays of this workload (same medium and settings)."""
         n = min(n, self.n)

@@ -176,3 +176,30 @@ def test_autograd_function_matches_adjoint():
     loss.backward()
     assert np.allclose(k0r.grad.cpu().numpy(), g["gk0"], rtol=0, atol=1e-13)
     assert np.allclose(coef.grad.cpu().numpy(), g["gp"][0], rtol=1e-12, atol=1e-13)
+
+
+def test_aniso_full_size_sampled(oracle):
+    """Full workload 5 (1,048,576 rays, 20,000 steps, checkpoints every
+    100) forward and adjoint in the benchmark's launch configuration; the
+    endpoints and the per-ray gradients dL/dx0, dL/dk0 of 96 sampled rays
+    recomputed by the oracle (the parameter gradient sums all rays and is
+    checked at smaller sizes above)."""
+    torch = U.torch_mod()
+    w = W.make("5")
+    print(f"[case] aniso full size n={w.n} steps={w.n_steps}", flush=True)
+    g = _gpu_grad(w, ckpt=w.ckpt_every)
+    idx = np.sort(np.random.default_rng(43).choice(w.n, 96, replace=False))
+    ws = w.select(idx)
+    bad, o = U.ill_conditioned(oracle, ws)
+    gx = {"x": g["x"][:, idx]}
+    ex = np.linalg.norm(gx["x"] - o["x"], axis=0) / np.maximum(np.linalg.norm(o["x"], axis=0), 1.0)
+    ok = ~bad
+    print(f"ill-conditioned: {bad.sum()}, max e_x {ex[ok].max():.2e}", flush=True)
+    assert ex[ok].max() < U.TOL
+    lam = np.concatenate([2 * (o["x"] - ws.targets), np.zeros_like(o["k"])])
+    lam0, _ = oracle.adjoint(ws, lam)
+    for got, ref in ((g["gx0"][:, idx], lam0[: w.dim]), (g["gk0"][:, idx], lam0[w.dim:])):
+        rel = np.abs(got - ref).max(axis=0)[ok] / np.maximum(np.abs(ref).max(axis=0)[ok], 1e-300)
+        assert rel.max() < ORACLE_TOL, rel.max()
+    del g
+    torch.cuda.empty_cache()

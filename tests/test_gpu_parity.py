@@ -127,6 +127,29 @@ def test_dopri_bumps_subset(oracle):
     assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
 
 
+def test_bumps_full_size_sampled(oracle):
+    """Full workload 3 (4,194,304 rays, adaptive Dormand-Prince, box and
+    lognormal budgets, persistent launch with refill) in the benchmark's
+    launch configuration; 512 sampled rays recomputed by the oracle."""
+    w = W.make("3")
+    _print_case("bumps_full", w)
+    torch = U.torch_mod()
+    g = U.gpu_trace(w)
+    idx = np.sort(np.random.default_rng(41).choice(w.n, 512, replace=False))
+    ws = w.select(idx)
+    bad, o = U.ill_conditioned(oracle, ws)
+    gs = {k: (g[k][..., idx] if k in ("x", "k", "status", "steps", "attempts") else None)
+          for k in ("x", "k", "status", "steps", "attempts")}
+    same = (gs["status"] == o["status"]) & (gs["steps"] == o["steps"]) & (gs["attempts"] == o["attempts"])
+    print(f"ill-conditioned: {bad.sum()}, status/steps mismatches: {(~same).sum()}", flush=True)
+    assert same.mean() >= 0.99
+    ex, ek = U.ray_errors(gs, o, ws.omega, w.dim)
+    ok = same & ~bad
+    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+    del g
+    torch.cuda.empty_cache()
+
+
 def test_reciprocal_within_one_ulp():
     """The emitted reciprocal of dD/domega (hardware estimate + two Newton
     steps) is within 1 ulp of the correctly rounded 1/d: homogeneous medium,
