@@ -439,15 +439,18 @@ __device__ __forceinline__ void rg_dp_attempt(const rg_kargs &a, const rg_P &P, 
     }
     const double err = sqrt(sum / (double)RG_NY);
     r.att++;
-    if (err <= 1.0 && rg_finite(y5) && rg_finite(k7)) {
+    // one step factor for both outcomes (lanes of a wave take both branches,
+    // so a factor computed in each would cost two pow per attempt)
+    const bool ok = err <= 1.0 && rg_finite(y5) && rg_finite(k7);
+    const double fac = rg_dp_factor(ok ? err : (err > 1.0 ? err : __builtin_inf()), ok ? r.fm : 1.0);
+    r.h = hs * fac;
+    if (ok) {
         for (int i = 0; i < RG_NY; i++) { r.y[i] = y5[i]; r.k1[i] = k7[i]; }
         r.t = r.t + hs;
         r.acc++;
-        r.h = hs * rg_dp_factor(err, r.fm);
         r.fm = 5.0;
         if (a.has_box && rg_outside(a, r.y)) { r.st = RG_RAY_EXITED_BOX; return; }
     } else {
-        r.h = hs * rg_dp_factor(err > 1.0 ? err : __builtin_inf(), 1.0);
         r.fm = 1.0;
     }
     if (r.h < a.hmin) r.st = RG_RAY_STEP_UNDERFLOW;
