@@ -207,7 +207,8 @@ def main():
             traffic = float(kv["hbm_bytes_per_launch"])
 
     result = {
-        "metric": "FP64 ray-steps/s (persistent fused RK4, one launch per trace)",
+        "metric": ("FP64 ray-steps/s (persistent fused RK4, one launch per trace)" if w.integrator == W.RK4 else
+                   "FP64 accepted ray-steps/s (persistent Dormand-Prince 5(4) with in-kernel refill)"),
         "value": value, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
