@@ -169,7 +169,9 @@ typedef struct {
  * kernels and compile for gfx950 with hipRTC.  The graph must outlive
  * nothing: the program keeps its own copy of what it needs.  A failed
  * hipRTC compile returns RG_ECOMPILE with the compiler log in
- * rg_last_error(). */
+ * rg_last_error().  Code objects are cached by generated source, compile
+ * options and hipRTC version, in the process and, if the environment
+ * variable RAYGRAPH_CODE_CACHE names a directory, on disk there. */
 rg_status rg_compile(rg_graph *g, rg_node D, const rg_compile_opts *opts, rg_program **out);
 rg_status rg_destroy_program(rg_program *p);
 

@@ -14,6 +14,11 @@
 #include <cstdlib>
 
 #include <chrono>
+#include <cstdio>
+#include <thread>
+#include <mutex>
+#include <map>
+#include <fstream>
 #include <cstring>
 #include <sstream>
 
@@ -40,6 +45,57 @@ static std::string int_array(const char *name, const std::vector<int> &v) {
     for (size_t i = 0; i < v.size(); i++) os << (i ? ", " : "") << v[i];
     os << "};\n";
     return os.str();
+}
+
+// ------------------------------------------------------ code-object cache
+
+static std::mutex g_cache_mu;
+static std::map<uint64_t, std::vector<char>> g_code_cache;
+
+static std::string cache_path(uint64_t key) {
+    const char *dir = std::getenv("RAYGRAPH_CODE_CACHE");
+    if (!dir || !*dir) return std::string();
+    char name[40];
+    std::snprintf(name, sizeof name, "/%016llx.co", (unsigned long long)key);
+    return std::string(dir) + name;
+}
+
+static bool code_cache_get(uint64_t key, std::vector<char> *code) {
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_code_cache.find(key);
+        if (it != g_code_cache.end()) {
+            *code = it->second;
+            return true;
+        }
+    }
+    const std::string path = cache_path(key);
+    if (path.empty()) return false;
+    std::ifstream in(path, std::ios::binary);
+    if (!in) return false;
+    std::vector<char> buf((std::istreambuf_iterator<char>(in)), std::istreambuf_iterator<char>());
+    if (buf.size() < 64) return false;  // not a code object
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_code_cache[key] = buf;
+    *code = std::move(buf);
+    return true;
+}
+
+static void code_cache_put(uint64_t key, const std::vector<char> &code) {
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_code_cache[key] = code;
+    }
+    const std::string path = cache_path(key);
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp" + std::to_string((unsigned long long)std::hash<std::thread::id>()(std::this_thread::get_id()));
+    {
+        std::ofstream out(tmp, std::ios::binary);
+        if (!out) return;
+        out.write(code.data(), (std::streamsize)code.size());
+        if (!out) return;
+    }
+    std::rename(tmp.c_str(), path.c_str());  // atomic replace; a failure leaves no cache entry
 }
 
 // Products of every function are re-associated before emission (shared
@@ -303,10 +359,6 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     std::string arch_opt = std::string("--offload-arch=") + arch;
     int olvl = opts.opt_level > 0 ? opts.opt_level : 3;
     std::string o_opt = "-O" + std::to_string(olvl);
-    hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, p->full_src.c_str(), "raygraph_kernels.hip", 0, nullptr, nullptr) !=
-        HIPRTC_SUCCESS)
-        return fail(RG_ECOMPILE, "hiprtcCreateProgram failed");
     // no FP contraction beyond the fma written in the source; no packed FP32
     // With rolled stage loops, machine-level loop-invariant code motion is
     // off: it would hoist every constant's scalar-register materialization
@@ -314,7 +366,24 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     const char *copts[] = {arch_opt.c_str(), o_opt.c_str(), "-ffp-contract=off", "-std=c++17",
                            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                            "-mllvm", "-disable-machine-licm"};
-    hiprtcResult rc = hiprtcCompileProgram(prog, p->rolled ? 10 : 8, copts);
+    const int ncopts = p->rolled ? 10 : 8;
+    // code objects are cached by source and options (in the process, and in
+    // the directory RAYGRAPH_CODE_CACHE if set)
+    int rtc_major = 0, rtc_minor = 0;
+    hiprtcVersion(&rtc_major, &rtc_minor);
+    std::string key_text = p->full_src;
+    for (int i = 0; i < ncopts; i++) key_text += std::string("\n") + copts[i];
+    key_text += "\nhiprtc " + std::to_string(rtc_major) + "." + std::to_string(rtc_minor);
+    const uint64_t key = fnv1a(key_text.data(), key_text.size());
+    if (code_cache_get(key, &p->code)) {
+        I.compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return RG_OK;
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, p->full_src.c_str(), "raygraph_kernels.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS)
+        return fail(RG_ECOMPILE, "hiprtcCreateProgram failed");
+    hiprtcResult rc = hiprtcCompileProgram(prog, ncopts, copts);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
@@ -328,6 +397,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     p->code.resize(cs_);
     hiprtcGetCode(prog, p->code.data());
     hiprtcDestroyProgram(&prog);
+    code_cache_put(key, p->code);
     I.compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return RG_OK;
 }

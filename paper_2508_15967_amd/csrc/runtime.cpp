@@ -2,6 +2,7 @@
 // sequences (persistent or one-launch-per-step), hipGraph capture and
 // replay, autotuning, and the adjoint pass.
 #include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
 
 #include <algorithm>
 #include <cmath>
@@ -345,8 +346,11 @@ static rg_status time_seq(rg_program *p, const std::vector<Launch> &seq, hipStre
 static std::string tune_key(rg_program *p, const char *what, long long n) {
     int lg = 0;
     while ((1ll << (lg + 1)) <= n) lg++;
-    char buf[160];
-    std::snprintf(buf, sizeof buf, "%016llx|%s|n2^%d|cu%d|gfx950", (unsigned long long)p->hash, what, lg, p->n_cu);
+    int rtc_major = 0, rtc_minor = 0;
+    hiprtcVersion(&rtc_major, &rtc_minor);
+    char buf[192];
+    std::snprintf(buf, sizeof buf, "%016llx|%s|n2^%d|cu%d|gfx950|hiprtc%d.%d", (unsigned long long)p->hash, what,
+                  lg, p->n_cu, rtc_major, rtc_minor);
     return buf;
 }
 
