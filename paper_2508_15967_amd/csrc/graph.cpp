@@ -316,6 +316,42 @@ std::vector<uint32_t> Graph::adjoints(const std::vector<uint32_t> &outs,
     return adj;
 }
 
+// ------------------------------------------------------ hoist divisions ---
+
+std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots) {
+    const std::vector<uint32_t> order = reachable(roots);
+    const size_t N0 = nodes_.size();
+    std::vector<char> inv(N0, 0);
+    std::vector<uint32_t> nw(N0, NONE);
+    for (uint32_t n : order) {
+        const Node d = nodes_[n];  // copy: factories may grow nodes_
+        if (d.op == CONST || d.op == PARAM) inv[n] = 1;
+        else if (d.op == VAR) inv[n] = d.aux / 8 == VK_OMEGA;
+        else inv[n] = (d.a == NONE || inv[d.a]) && (d.b == NONE || inv[d.b]);
+        if (d.op == CONST || d.op == VAR || d.op == PARAM) {
+            nw[n] = n;
+            continue;
+        }
+        const uint32_t a = d.a != NONE ? nw[d.a] : NONE, b = d.b != NONE ? nw[d.b] : NONE;
+        switch (d.op) {
+        case ADD: nw[n] = add(a, b); break;
+        case SUB: nw[n] = sub(a, b); break;
+        case MUL: nw[n] = mul(a, b); break;
+        case DIV:
+            nw[n] = !inv[d.a] && inv[d.b] && !is_const(b) && !is_const(a, 1.0) ? mul(a, div(constant(1.0), b))
+                                                                              : div(a, b);
+            break;
+        case NEG: nw[n] = neg(a); break;
+        case POWI: nw[n] = powi(a, d.aux); break;
+        case SPLINE: nw[n] = spline((uint32_t)d.val, d.aux / 4, d.aux % 4, a, b); break;
+        default: nw[n] = unary(d.op, a); break;
+        }
+    }
+    std::vector<uint32_t> out(roots.size(), NONE);
+    for (size_t i = 0; i < roots.size(); i++) out[i] = roots[i] == NONE ? NONE : nw[roots[i]];
+    return out;
+}
+
 // ------------------------------------------------------ factor products ---
 
 std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots) {

@@ -94,6 +94,12 @@ public:
     // x + x reduces to 2x).
     std::vector<uint32_t> factor_sums(const std::vector<uint32_t> &roots);
 
+    // A division whose denominator is invariant along a ray (built from
+    // omega, parameters and constants only) and whose numerator is not
+    // becomes a product with the reciprocal, which the compiler then
+    // computes once per ray instead of once per evaluation.
+    std::vector<uint32_t> hoist_divisions(const std::vector<uint32_t> &roots);
+
     bool is_const(uint32_t n) const { return nodes_[n].op == CONST; }
     bool is_const(uint32_t n, double v) const {
         return nodes_[n].op == CONST && nodes_[n].val == v;

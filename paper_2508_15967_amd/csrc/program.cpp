@@ -108,7 +108,7 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool table_exp) {
         roots.push_back(s.seed);
         roots.push_back(s.spline_node);
     }
-    const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(roots));
+    const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(g.hoist_divisions(roots)));
     size_t k = 0;
     for (Output &o : spec.outputs) o.node = nr[k++];
     for (SplineSeed &s : spec.spline_seeds) {

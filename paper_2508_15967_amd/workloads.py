@@ -318,6 +318,10 @@ def make(cfg: str, n_rays: Optional[int] = None) -> Workload:
         return spline2d(n_rays)
     if cfg == "5":
         return aniso3d(n_rays)
+    if cfg == "cp":
+        # the paper's own physics at its benchmark scale: 1,048,576 O-mode
+        # rays in the cold-plasma slab, to the plasma cut-off and back
+        return coldplasma("O", n_rays if n_rays is not None else 1048576, dt=1e-2, n_steps=4000)
     raise ValueError(f"unknown workload {cfg!r}")
 
 

@@ -61,3 +61,21 @@ def test_X_mode_reflects_at_L_cutoff(oracle):
     x = g["traj"][:, 0]
     assert np.all(x.max(0) < 20.0) and np.all(x.max(0) > 19.5)
     assert np.all(g["k"][0] < 0)                 # turned around
+
+
+def test_coldplasma_full_size_sampled(oracle):
+    """The cold-plasma benchmark workload at its full size (1,048,576 O-mode
+    rays, 4,000 steps) in the benchmark's launch configuration; 128 sampled
+    rays recomputed by the oracle."""
+    torch = U.torch_mod()
+    w = W.make("cp")
+    print(f"[case] coldplasma full size n={w.n} steps={w.n_steps}", flush=True)
+    g = U.gpu_trace(w)
+    idx = np.sort(np.random.default_rng(47).choice(w.n, 128, replace=False))
+    ws = w.select(idx)
+    o = oracle.trace(ws)
+    ex, ek = U.ray_errors({"x": g["x"][:, idx], "k": g["k"][:, idx]}, o, ws.omega, w.dim)
+    assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
+    assert np.array_equal(g["t"][idx], o["t"])
+    del g
+    torch.cuda.empty_cache()
