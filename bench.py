@@ -177,9 +177,15 @@ def main():
         attempts = int(outs["attempts_out"].cpu().numpy().astype(np.int64).sum())
         flops_alg = info["dopri_attempt_flops_alg"] * attempts
         flops_iss = info["dopri_attempt_flops_issued"] * attempts
+    # ray-invariant operations (constants, parameters, omega only) run once
+    # per ray, outside the step loop
+    inv_fwd = info["rhs_flops_ray_invariant"] * n
+    flops_alg += inv_fwd
+    flops_iss += inv_fwd
     if adjoint:
-        flops_alg_adj = info["adj_step_flops_alg"] * ray_steps
-        flops_iss_adj = info["adj_step_flops_issued"] * ray_steps
+        inv_adj = (info["rhs_flops_ray_invariant"] + info["vjp_flops_ray_invariant"]) * n
+        flops_alg_adj = info["adj_step_flops_alg"] * ray_steps + inv_adj
+        flops_iss_adj = info["adj_step_flops_issued"] * ray_steps + inv_adj
     # the roofline entry is for the dominant kernel of one step
     if w.integrator == W.RK4:
         kname = "rg_rk4_r%d" % launch["rays_per_lane"]

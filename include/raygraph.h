@@ -193,6 +193,10 @@ typedef struct {
     double adj_step_flops_alg, adj_step_flops_issued; /* reverse of one RK4 step incl. recompute */
     uint64_t source_hash;
     double compile_ms;
+    /* flops ("alg") of operations on values that depend only on constants,
+       parameters and omega: invariant along a ray, computed once per ray by
+       the integrator loops and excluded from the per-evaluation counts above */
+    double rhs_flops_ray_invariant, vjp_flops_ray_invariant;
 } rg_program_info;
 rg_status rg_program_info_get(const rg_program *p, rg_program_info *out);
 /* Borrowed pointer to the full generated HIP source; valid while p lives. */

@@ -72,6 +72,7 @@ struct Emitter {
         uint32_t root;
         std::vector<std::pair<uint32_t, int>> leaves;  // term node, sign
         bool started = false;
+        bool acc_inv = true;  // every term accumulated so far is ray-invariant
     };
     std::vector<Chain> chains;
     std::vector<int> chain_of_root;  // node -> chain index or -1
@@ -79,6 +80,8 @@ struct Emitter {
     std::vector<uint32_t> consumer;  // unique consumer of a single-use node
     bool f32 = false;                // emit single precision (float) code
     bool table_exp = true;           // rg_exp rather than the library exp
+    std::vector<char> inv;           // value depends only on constants, parameters, omega
+    bool cur_inv = false;            // the operation being counted is ray-invariant
 
     const char *T() const { return f32 ? "float" : "double"; }
     std::string lit(double v) const { return f32 ? hex_float(v) : hex_double(v); }
@@ -110,28 +113,33 @@ struct Emitter {
         return "v" + std::to_string(n);
     }
 
+    // Counted into the ray-invariant part while cur_inv is set.
+    void tally(double alg, double iss) {
+        if (cur_inv) { fl.inv_alg += alg; fl.inv_issued += iss; }
+        else { fl.alg += alg; fl.issued += iss; }
+    }
     void count(int op, int aux = 0) {
         const IssuedWeights &w = issued_weights();
         fl.ops++;
         switch (op) {
-        case ADD: case SUB: case MUL: fl.alg += 1; fl.issued += 1; break;
-        case DIV: fl.alg += 1; fl.issued += w.div; break;
-        case EXP: fl.alg += 1; fl.issued += table_exp || f32 ? w.exp : w.exp_lib; break;
-        case LOG: fl.alg += 1; fl.issued += w.log; break;
-        case SQRT: fl.alg += 1; fl.issued += w.sqrt; break;
-        case SIN: case COS: fl.alg += 1; fl.issued += w.sincos; break;
+        case ADD: case SUB: case MUL: tally(1, 1); break;
+        case DIV: tally(1, w.div); break;
+        case EXP: tally(1, table_exp || f32 ? w.exp : w.exp_lib); break;
+        case LOG: tally(1, w.log); break;
+        case SQRT: tally(1, w.sqrt); break;
+        case SIN: case COS: tally(1, w.sincos); break;
         case POWI: {
             int n = aux < 0 ? -aux : aux;
-            fl.alg += n - 1; fl.issued += n - 1;
-            if (aux < 0) { fl.alg += 1; fl.issued += w.div; }
+            tally(n - 1, n - 1);
+            if (aux < 0) tally(1, w.div);
             break;
         }
         case NEG: fl.ops--; break;
         default: break;
         }
     }
-    void count_fma(int n = 1) { fl.alg += 2 * n; fl.issued += 2 * n; fl.ops += n; }
-    void count_plain(double f) { fl.alg += f; fl.issued += f; }
+    void count_fma(int n = 1) { tally(2 * n, 2 * n); fl.ops += n; }
+    void count_plain(double f) { tally(f, f); }
 
     bool fusable_mul(uint32_t m) const {
         const Node &nd = g.node(m);
@@ -139,6 +147,13 @@ struct Emitter {
     }
 
     void plan(const std::vector<uint32_t> &order, const std::vector<uint32_t> &roots) {
+        inv.assign(g.size(), 0);
+        for (uint32_t n : order) {
+            const Node &nd = g.node(n);
+            if (nd.op == CONST || nd.op == PARAM) inv[n] = 1;
+            else if (nd.op == VAR) inv[n] = nd.aux / 8 == VK_OMEGA;
+            else inv[n] = (nd.a == NONE || inv[nd.a]) && (nd.b == NONE || inv[nd.b]);
+        }
         for (uint32_t n : order) {
             const Node &nd = g.node(n);
             if (nd.a != NONE) uses[nd.a]++;
@@ -253,6 +268,7 @@ struct Emitter {
         const Node &nd = g.node(n);
         if (emitted[n]) return;
         emitted[n] = 1;
+        cur_inv = inv[n];
         switch (nd.op) {
         case CONST: case VAR:
             return;
@@ -331,6 +347,8 @@ struct Emitter {
         const int sg = c.leaves[li].second;
         const std::string R = name(c.root);
         const bool prod = fused[leaf] && g.node(leaf).op == MUL;
+        c.acc_inv = c.acc_inv && inv[leaf];
+        cur_inv = c.acc_inv;
         if (!c.started) {
             c.started = true;
             std::string t;
@@ -368,6 +386,7 @@ struct Emitter {
     // operations move; sums are reassociated (deterministically).
     // One output statement ("lhs = v;" or "lhs += v;").
     void emit_output(const Output &o) {
+        cur_inv = false;
         if (o.accumulate) {
             if (!g.is_const(o.node, 0.0)) {
                 os << "  " << o.lhs << " += " << name(o.node) << ";\n";
@@ -590,6 +609,7 @@ struct Emitter {
     // Gradient scatter of spline coefficients: for each cell group, the 16
     // coefficient gradients sum_n seed_n * scale_n * wx_du[a] * wy_dv[b].
     void emit_spline_grads(const std::vector<SplineSeed> &seeds) {
+        cur_inv = false;
         std::map<int, std::vector<SplineSeed>> by_group;
         for (const SplineSeed &s : seeds) {
             if (g.is_const(s.seed, 0.0)) continue;

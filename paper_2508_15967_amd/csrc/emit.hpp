@@ -16,11 +16,14 @@
 
 namespace rg {
 
+// Operations on values that depend only on constants, parameters and omega
+// are invariant along a ray: the integrator loop computes them once per ray,
+// so they are counted apart (inv_*) from the work of one evaluation.
 struct Flops {
     double alg = 0.0;     // add/sub/mul/div/sqrt/exp/... = 1, fma = 2
     double issued = 0.0;  // FP64 add/mul/fma flops of the gfx950 expansion
-    uint32_t ops = 0;     // emitted operations
-    void add(const Flops &o) { alg += o.alg; issued += o.issued; ops += o.ops; }
+    uint32_t ops = 0;     // emitted operations (ray-invariant ones included)
+    double inv_alg = 0.0, inv_issued = 0.0;  // ray-invariant part, not in alg/issued
 };
 
 // Issued FP64 flops of one operation's instruction expansion on gfx950

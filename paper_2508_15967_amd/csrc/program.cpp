@@ -283,7 +283,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     // sides cost less than waiting for them from the segment buffer (a few
     // hundred issued flops against a global-memory latency the few waves of
     // a small ray batch cannot hide); otherwise they are stored.
-    p->adj_recompute = fl_rhs.issued < 400.0;
+    p->adj_recompute = fl_rhs.issued + fl_rhs.inv_issued < 400.0;
 
     // ---- configuration header
     std::ostringstream cs;
@@ -309,6 +309,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     I.n_grad_slots = (uint32_t)p->grad_param.size();
     I.rhs_flops_alg = fl_rhs.alg;
     I.rhs_flops_issued = fl_rhs.issued;
+    I.rhs_flops_ray_invariant = fl_rhs.inv_alg;
     // RK4 update: per component 3 stage fma + fma, fma, add + final fma = 13
     // flops, plus t += dt and the two step constants.
     const double upd = 13.0 * ny + 1.0;
@@ -326,6 +327,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     if (p->has_vjp) {
         I.vjp_flops_alg = fl_vjp.alg;
         I.vjp_flops_issued = fl_vjp.issued;
+        I.vjp_flops_ray_invariant = fl_vjp.inv_alg;
         // reverse of one step: recompute (one RK4 step) [+ 3 stage RHS and
         // 3 stage fma when the stages are recomputed] + 4 VJP + recurrence
         // (per component: 3 fma, 3 add, 1 mul, 1 add = 12 flops)

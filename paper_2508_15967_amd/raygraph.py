@@ -89,7 +89,8 @@ class _ProgramInfo(C.Structure):
                 ("dopri_attempt_flops_alg", C.c_double), ("dopri_attempt_flops_issued", C.c_double),
                 ("vjp_flops_alg", C.c_double), ("vjp_flops_issued", C.c_double),
                 ("adj_step_flops_alg", C.c_double), ("adj_step_flops_issued", C.c_double),
-                ("source_hash", C.c_uint64), ("compile_ms", C.c_double)]
+                ("source_hash", C.c_uint64), ("compile_ms", C.c_double),
+                ("rhs_flops_ray_invariant", C.c_double), ("vjp_flops_ray_invariant", C.c_double)]
 
 
 class _NodeDesc(C.Structure):

@@ -247,3 +247,20 @@ def test_exp_host_accuracy():
     fin = np.isfinite(ref_sp) & (ref_sp > 0)
     same |= fin & (_exp_ulps(got_sp, ref_sp) <= 1.5)
     assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+
+
+def test_ray_invariant_flops_counted_apart():
+    """Operations on omega alone run once per ray: the emitted right-hand side
+    of D = k.k - omega^2 (1 + x/2) has three of them (2 omega, omega/2,
+    omega * omega/2), counted apart from the per-evaluation flops."""
+    from paper_2508_15967_amd import raygraph as rgb
+    counts = []
+    for square in (False, True):
+        g = rgb.Graph(2)
+        w2 = g.omega * g.omega if square else g.omega
+        D = g.k(0) * g.k(0) + g.k(1) * g.k(1) - w2 * (1.0 + 0.5 * g.x(0))
+        info = g.compile(D, compile_only=True).info()
+        counts.append((info["rhs_flops_alg"], info["rhs_flops_ray_invariant"]))
+    assert counts[0][1] == 1.0 and counts[1][1] == 3.0, counts
+    # the per-evaluation part differs only by the product (1 + x/2)(2 omega)
+    assert counts[1][0] == counts[0][0] + 1.0, counts
