@@ -318,7 +318,7 @@ std::vector<uint32_t> Graph::adjoints(const std::vector<uint32_t> &outs,
 
 // ------------------------------------------------------ hoist divisions ---
 
-std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots) {
+std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots, bool split_products) {
     const std::vector<uint32_t> order = reachable(roots);
     const size_t N0 = nodes_.size();
     std::vector<char> inv(N0, 0);
@@ -337,10 +337,39 @@ std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots)
         case ADD: nw[n] = add(a, b); break;
         case SUB: nw[n] = sub(a, b); break;
         case MUL: nw[n] = mul(a, b); break;
-        case DIV:
-            nw[n] = !inv[d.a] && inv[d.b] && !is_const(b) && !is_const(a, 1.0) ? mul(a, div(constant(1.0), b))
-                                                                              : div(a, b);
+        case DIV: {
+            if (inv[d.b] || !split_products) {
+                nw[n] = inv[d.b] && !inv[d.a] && !is_const(b) && !is_const(a, 1.0) ? mul(a, div(constant(1.0), b)) : div(a, b);
+                break;
+            }
+            // a variant denominator that is a product with invariant factors:
+            // a / (I V) = (a / V) (1 / I), the second factor once per ray
+            std::vector<uint32_t> fi, fv;
+            bool negate = false;
+            std::function<void(uint32_t)> walk = [&](uint32_t m) {
+                const Node &q = nodes_[m];
+                if (q.op == MUL && fi.size() + fv.size() < 32) {
+                    walk(q.a);
+                    walk(q.b);
+                } else if (q.op == NEG) {
+                    negate = !negate;
+                    walk(q.a);
+                } else {
+                    (inv[m] ? fi : fv).push_back(nw[m]);
+                }
+            };
+            walk(d.b);
+            if (fi.empty() || fv.empty()) {
+                nw[n] = div(a, b);
+                break;
+            }
+            uint32_t pv = fv[0], pi = fi[0];
+            for (size_t i = 1; i < fv.size(); i++) pv = mul(pv, fv[i]);
+            for (size_t i = 1; i < fi.size(); i++) pi = mul(pi, fi[i]);
+            if (negate) pi = neg(pi);
+            nw[n] = mul(div(a, pv), div(constant(1.0), pi));
             break;
+        }
         case NEG: nw[n] = neg(a); break;
         case POWI: nw[n] = powi(a, d.aux); break;
         case SPLINE: nw[n] = spline((uint32_t)d.val, d.aux / 4, d.aux % 4, a, b); break;
@@ -354,7 +383,7 @@ std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots)
 
 // ------------------------------------------------------ factor products ---
 
-std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots) {
+std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots, bool merge_invariants) {
     const std::vector<uint32_t> order = reachable(roots);
     const size_t N0 = nodes_.size();
     auto is_prod = [&](uint32_t n) {
@@ -421,58 +450,129 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots)
         prod_of[n] = (int)prods.size();
         prods.push_back(std::move(P));
     }
-    // greedy pairing (most shared pair first, ties to the smaller pair)
-    std::vector<std::pair<uint32_t, uint32_t>> pairs;
-    for (;;) {
-        std::map<std::pair<uint32_t, uint32_t>, int> count;
-        for (const Prod &P : prods) {
-            std::set<std::pair<uint32_t, uint32_t>> here;
-            for (size_t i = 0; i < P.sym.size(); i++)
-                for (size_t j = i + 1; j < P.sym.size(); j++) here.insert({P.sym[i], P.sym[j]});
-            for (const auto &pr : here) count[pr]++;
-        }
-        std::pair<uint32_t, uint32_t> best{0, 0};
-        int bc = 1;
-        for (const auto &kv : count)
-            if (kv.second > bc) {
-                bc = kv.second;
-                best = kv.first;
-            }
-        if (bc < 2) break;
-        const uint32_t v = kVirtual | (uint32_t)pairs.size();
-        pairs.push_back(best);
-        for (Prod &P : prods) {
-            // every disjoint occurrence (x y x y holds the pair twice)
-            for (;;) {
-                auto ia = std::find(P.sym.begin(), P.sym.end(), best.first);
-                if (ia == P.sym.end()) break;
-                auto ib = std::find(ia + 1, P.sym.end(), best.second);
-                if (ib == P.sym.end()) break;
-                P.sym.erase(ib);
-                P.sym.erase(ia);
-                P.sym.push_back(v);
-                std::sort(P.sym.begin(), P.sym.end());
-            }
-        }
-    }
     // factors are multiplied in order of variability: constants, then what
-    // depends only on omega, t and parameters (invariant along a ray: the
+    // depends only on omega and parameters (invariant along a ray: the
     // compiler hoists that part of the product out of the time loop), then
-    // what depends on the state or the seeds
+    // what depends on the state, t or the seeds
     std::vector<int> rank(N0, 0);
     for (uint32_t n : order) {
         const Node &d = nodes_[n];
-        if (d.op == VAR) rank[n] = (d.aux / 8 == VK_OMEGA || d.aux / 8 == VK_T) ? 1 : 2;
+        if (d.op == VAR) rank[n] = d.aux / 8 == VK_OMEGA ? 1 : 2;
         else if (d.op == PARAM) rank[n] = 1;
         else if (d.op != CONST)
             rank[n] = std::max(d.a != NONE ? rank[d.a] : 0, d.b != NONE ? rank[d.b] : 0);
     }
+    auto leaf_rank = [&](uint32_t s2) { return s2 < N0 ? rank[s2] : 0; };  // new nodes: folded constants
+    // Greedy pairing (most shared pair first, ties to the smaller pair),
+    // tried two ways: as is, and with the invariant factors of each product
+    // made one factor first.  The second keeps every invariant factor out of
+    // the time loop, while the first may share a pair of an invariant and a
+    // variant factor between products; the one with fewer multiplications
+    // per evaluation is kept.
+    struct Pairing {
+        std::vector<std::pair<uint32_t, uint32_t>> pairs;
+        std::vector<Prod> prods;
+    };
+    auto srank_of = [&](const Pairing &R) {
+        std::function<int(uint32_t)> f = [&R, &f, &leaf_rank](uint32_t s2) -> int {
+            if (s2 & kVirtual) {
+                const auto &pr = R.pairs[s2 & ~kVirtual];
+                return std::max(f(pr.first), f(pr.second));
+            }
+            return leaf_rank(s2);
+        };
+        return f;
+    };
+    auto run_pairing = [&](bool merge) {
+        Pairing R{{}, prods};
+        std::map<std::pair<uint32_t, uint32_t>, uint32_t> pair_id;
+        auto make_pair = [&](uint32_t x, uint32_t y) {
+            const std::pair<uint32_t, uint32_t> key{std::min(x, y), std::max(x, y)};
+            auto it = pair_id.find(key);
+            if (it != pair_id.end()) return it->second;
+            const uint32_t v = kVirtual | (uint32_t)R.pairs.size();
+            R.pairs.push_back(key);
+            pair_id[key] = v;
+            return v;
+        };
+        if (merge)
+            for (Prod &P : R.prods) {
+                std::vector<uint32_t> iv, vv;
+                for (uint32_t s2 : P.sym) (leaf_rank(s2) <= 1 ? iv : vv).push_back(s2);
+                if (iv.size() < 2) continue;
+                uint32_t acc = iv[0];
+                for (size_t i = 1; i < iv.size(); i++) acc = make_pair(acc, iv[i]);
+                vv.push_back(acc);
+                std::sort(vv.begin(), vv.end());
+                P.sym = std::move(vv);
+            }
+        for (;;) {
+            std::map<std::pair<uint32_t, uint32_t>, int> count;
+            for (const Prod &P : R.prods) {
+                std::set<std::pair<uint32_t, uint32_t>> here;
+                for (size_t i = 0; i < P.sym.size(); i++)
+                    for (size_t j = i + 1; j < P.sym.size(); j++) here.insert({P.sym[i], P.sym[j]});
+                for (const auto &pr : here) count[pr]++;
+            }
+            std::pair<uint32_t, uint32_t> best{0, 0};
+            int bc = 1;
+            for (const auto &kv : count)
+                if (kv.second > bc) {
+                    bc = kv.second;
+                    best = kv.first;
+                }
+            if (bc < 2) break;
+            const uint32_t v = make_pair(best.first, best.second);
+            for (Prod &P : R.prods) {
+                // every disjoint occurrence (x y x y holds the pair twice)
+                for (;;) {
+                    auto ia = std::find(P.sym.begin(), P.sym.end(), best.first);
+                    if (ia == P.sym.end()) break;
+                    auto ib = std::find(ia + 1, P.sym.end(), best.second);
+                    if (ib == P.sym.end()) break;
+                    P.sym.erase(ib);
+                    P.sym.erase(ia);
+                    P.sym.push_back(v);
+                    std::sort(P.sym.begin(), P.sym.end());
+                }
+            }
+        }
+        return R;
+    };
+    // multiplications per evaluation: in a product of m factors, k of them
+    // invariant, the k - 1 among the invariant ones are hoisted; a formed
+    // pair costs one if either side varies
+    auto per_eval_muls = [&](const Pairing &R) {
+        auto sr = srank_of(R);
+        size_t c = 0;
+        std::set<uint32_t> used;
+        std::function<void(uint32_t)> mark = [&](uint32_t s2) {
+            if (!(s2 & kVirtual) || !used.insert(s2).second) return;
+            mark(R.pairs[s2 & ~kVirtual].first);
+            mark(R.pairs[s2 & ~kVirtual].second);
+        };
+        for (const Prod &P : R.prods) {
+            size_t k = 0;
+            for (uint32_t s2 : P.sym) {
+                k += sr(s2) <= 1;
+                mark(s2);
+            }
+            if (!P.sym.empty()) c += P.sym.size() - 1 - (k > 0 ? k - 1 : 0);
+        }
+        for (uint32_t v : used) c += sr(v) > 1;
+        return c;
+    };
+    Pairing plain = run_pairing(false), merged;
+    if (merge_invariants) merged = run_pairing(true);
+    Pairing &chosen = merge_invariants && per_eval_muls(merged) < per_eval_muls(plain) ? merged : plain;
+    std::vector<std::pair<uint32_t, uint32_t>> pairs = std::move(chosen.pairs);
+    prods = std::move(chosen.prods);
     std::function<int(uint32_t)> srank = [&](uint32_t s2) -> int {
         if (s2 & kVirtual) {
             const auto &pr = pairs[s2 & ~kVirtual];
             return std::max(srank(pr.first), srank(pr.second));
         }
-        return s2 < N0 ? rank[s2] : 0;  // new nodes here are folded constants
+        return leaf_rank(s2);
     };
     for (Prod &P : prods)
         std::stable_sort(P.sym.begin(), P.sym.end(),

@@ -85,7 +85,10 @@ public:
     // most shared pair first) and each product is rebuilt from them.  Other
     // nodes are rebuilt on the new operands.  Returns the roots' new nodes
     // (the old ones stay valid).  Reassociation changes rounding only.
-    std::vector<uint32_t> factor_products(const std::vector<uint32_t> &roots);
+    // With merge_invariants, a second pairing that first makes the
+    // ray-invariant factors of each product one factor is tried, and kept
+    // if it needs fewer multiplications per evaluation.
+    std::vector<uint32_t> factor_products(const std::vector<uint32_t> &roots, bool merge_invariants = true);
 
     // The same for sums: every maximal sum (ADD/SUB chains, negations
     // included) is flattened into signed terms, constant terms folded, term
@@ -97,8 +100,10 @@ public:
     // A division whose denominator is invariant along a ray (built from
     // omega, parameters and constants only) and whose numerator is not
     // becomes a product with the reciprocal, which the compiler then
-    // computes once per ray instead of once per evaluation.
-    std::vector<uint32_t> hoist_divisions(const std::vector<uint32_t> &roots);
+    // computes once per ray instead of once per evaluation; a variant
+    // denominator that is a product with invariant factors I keeps only
+    // its variant part V: a / (I V) = (a / V) (1 / I) (with split_products).
+    std::vector<uint32_t> hoist_divisions(const std::vector<uint32_t> &roots, bool split_products = true);
 
     bool is_const(uint32_t n) const { return nodes_[n].op == CONST; }
     bool is_const(uint32_t n, double v) const {

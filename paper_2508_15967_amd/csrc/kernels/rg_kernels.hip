@@ -70,7 +70,7 @@ struct rg_GA {
 #include "rg_functions.h"
 
 #if RG_USES_EXP
-__constant__ double rg_exp_const[64] = {RG_EXP_TABLE_VALUES};
+__constant__ double rg_exp_const[RG_EXP_N] = {RG_EXP_TABLE_VALUES};
 #endif
 
 // Copies the spline tables and the exponential's table into LDS (every
@@ -83,7 +83,7 @@ __device__ __forceinline__ void rg_stage_tables(const rg_kargs &a) {
     }
 #endif
 #if RG_USES_EXP
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) rg_exp_lds[i] = rg_exp_const[i];
+    for (int i = threadIdx.x; i < RG_EXP_N; i += blockDim.x) rg_exp_lds[i] = rg_exp_const[i];
 #endif
 #if RG_NSPLTAB > 0 || RG_USES_EXP
     __syncthreads();

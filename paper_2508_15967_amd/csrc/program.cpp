@@ -99,8 +99,12 @@ static void code_cache_put(uint64_t key, const std::vector<char> &code) {
 }
 
 // Products of every function are re-associated before emission (shared
-// factor pairs formed once; see Graph::factor_products).
-static void factor_spec(Graph &g, FunctionSpec &spec, bool table_exp) {
+// factor pairs formed once; see Graph::factor_products).  With `hoist`, the
+// ray-invariant parts of denominators and products are also split off so
+// that they are computed once per ray; each such value then stays live in
+// registers across the time loop, which the rolled programs (register
+// bound already) do not afford.
+static void factor_spec(Graph &g, FunctionSpec &spec, bool table_exp, bool hoist) {
     spec.table_exp = table_exp;
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);
@@ -108,7 +112,7 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool table_exp) {
         roots.push_back(s.seed);
         roots.push_back(s.spline_node);
     }
-    const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(g.hoist_divisions(roots)));
+    const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(g.hoist_divisions(roots, hoist)), hoist);
     size_t k = 0;
     for (Output &o : spec.outputs) o.node = nr[k++];
     for (SplineSeed &s : spec.spline_seeds) {
@@ -202,7 +206,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "RG_FN void rg_rhs(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, double *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_rhs);
     }
     if (opts.fp32) {
@@ -217,7 +221,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P, float *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         Flops fl32;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl32);
         p->has_f32 = true;
     }
@@ -228,7 +232,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
         spec.returns_value = true;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
     {
@@ -241,7 +245,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < d; i++)
             spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
         Flops fl_dk;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_dk);
     }
     p->info.n_nodes_rhs = fl_rhs.ops;
@@ -274,7 +278,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             const Node &nd = g.node(n);
             if (nd.op == SPLINE) spec.spline_seeds.push_back({n, A(n)});
         }
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
     }

@@ -250,17 +250,17 @@ def test_exp_host_accuracy():
 
 
 def test_ray_invariant_flops_counted_apart():
-    """Operations on omega alone run once per ray: the emitted right-hand side
-    of D = k.k - omega^2 (1 + x/2) has three of them (2 omega, omega/2,
-    omega * omega/2), counted apart from the per-evaluation flops."""
+    """Work on omega alone is done once per ray: for D = k.k - W(omega) (1 + x/2)
+    the right-hand side's per-evaluation flops do not depend on how the
+    frequency factor W is written (omega, omega^2, omega^3, omega^2 + 3 omega,
+    e^(omega/2)); what W adds is counted apart as ray-invariant."""
     from paper_2508_15967_amd import raygraph as rgb
     counts = []
-    for square in (False, True):
+    for wf in (lambda w: w, lambda w: w * w, lambda w: w * w * w, lambda w: w * w + 3.0 * w,
+               lambda w: (0.5 * w).exp()):
         g = rgb.Graph(2)
-        w2 = g.omega * g.omega if square else g.omega
-        D = g.k(0) * g.k(0) + g.k(1) * g.k(1) - w2 * (1.0 + 0.5 * g.x(0))
+        D = g.k(0) * g.k(0) + g.k(1) * g.k(1) - wf(g.omega) * (1.0 + 0.5 * g.x(0))
         info = g.compile(D, compile_only=True).info()
         counts.append((info["rhs_flops_alg"], info["rhs_flops_ray_invariant"]))
-    assert counts[0][1] == 1.0 and counts[1][1] == 3.0, counts
-    # the per-evaluation part differs only by the product (1 + x/2)(2 omega)
-    assert counts[1][0] == counts[0][0] + 1.0, counts
+    assert len({c[0] for c in counts}) == 1, counts
+    assert all(c[1] > counts[0][1] for c in counts[1:]), counts
