@@ -18,14 +18,13 @@ const IssuedWeights &issued_weights() {
     // v_div_fmas_f64 = 2; v_add_f64, v_mul_f64, v_rcp_f64, v_rsq_f64 = 1;
     // compares, class tests, ldexp/frexp, rounding, conversions and selects = 0.
     //   exp (rg_exp, table-driven): 6 fma + 2 mul = 14
-    //   exp (library): 13 fma + 1 mul             = 27
     //   div: 5 fma + div_fmas + mul + rcp = 14
     //   sqrt: 7 fma + 2 mul + rsq         = 17
     //   log: 14 fma + 43 add + 7 mul + rcp = 79
     //   sin/cos: 24 fma + 56 add + 11 mul = 115
     //   pow: 42 fma + 70 add + 11 mul + rcp = 166
     //   rg_rcp (reciprocal, rcp + two Newton steps): rcp + 4 fma = 9
-    static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 14.0, /*exp_lib*/ 27.0, /*log*/ 79.0, /*sqrt*/ 17.0,
+    static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 14.0, /*log*/ 79.0, /*sqrt*/ 17.0,
                                  /*sincos*/ 115.0, /*pow*/ 166.0, /*rcp*/ 9.0};
     return w;
 }
@@ -79,7 +78,6 @@ struct Emitter {
     std::vector<char> interior;      // node folded into a chain
     std::vector<uint32_t> consumer;  // unique consumer of a single-use node
     bool f32 = false;                // emit single precision (float) code
-    bool table_exp = true;           // rg_exp rather than the library exp
     std::vector<char> inv;           // value depends only on constants, parameters, omega
     bool cur_inv = false;            // the operation being counted is ray-invariant
 
@@ -124,7 +122,7 @@ struct Emitter {
         switch (op) {
         case ADD: case SUB: case MUL: tally(1, 1); break;
         case DIV: tally(1, w.div); break;
-        case EXP: tally(1, table_exp || f32 ? w.exp : w.exp_lib); break;
+        case EXP: tally(1, w.exp); break;
         case LOG: tally(1, w.log); break;
         case SQRT: tally(1, w.sqrt); break;
         case SIN: case COS: tally(1, w.sincos); break;
@@ -320,7 +318,7 @@ struct Emitter {
             }
             break;
         case NEG: e = "-" + A; break;
-        case EXP: e = (f32 ? "expf(" : table_exp ? "rg_exp(" : "exp(") + A + ")"; count(EXP); break;
+        case EXP: e = (f32 ? "expf(" : "rg_exp(") + A + ")"; count(EXP); break;
         case LOG: e = fn("log") + "(" + A + ")"; count(LOG); break;
         case SQRT: e = fn("sqrt") + "(" + A + ")"; count(SQRT); break;
         case SIN: e = fn("sin") + "(" + A + ")"; count(SIN); break;
@@ -672,7 +670,6 @@ std::string emit_function(const Graph &g, const FunctionSpec &spec,
                           const std::vector<int> &param_table_slot, Flops *flops) {
     Emitter em(g, param_table_slot);
     em.f32 = spec.fp32;
-    em.table_exp = spec.table_exp;
     if (spec.fp32 && !spec.spline_seeds.empty()) throw std::invalid_argument("single precision VJP");
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);

@@ -30,7 +30,7 @@ struct Flops {
 // (fma counted as 2, add/mul as 1; compares, selects, integer and exponent
 // manipulation count 0).
 struct IssuedWeights {
-    double div, exp, exp_lib, log, sqrt, sincos, pow, rcp;
+    double div, exp, log, sqrt, sincos, pow, rcp;
 };
 const IssuedWeights &issued_weights();
 
@@ -54,7 +54,6 @@ struct FunctionSpec {
     std::vector<SplineSeed> spline_seeds;  // VJP only
     bool returns_value = false;            // single output via "return"
     bool fp32 = false;                     // single precision (no spline nodes)
-    bool table_exp = true;                 // rg_exp (LDS table) instead of the library exp
 };
 
 // Emit a function.  `tables` maps a spline-definition's parameter to a table

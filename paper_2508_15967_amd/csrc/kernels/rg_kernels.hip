@@ -668,6 +668,23 @@ extern "C" __global__ void __launch_bounds__(512) rg_eval_points(rg_kargs a) {
 #define RG_NGRAD1 (RG_NGRAD > 0 ? RG_NGRAD : 1)
 __shared__ double rg_red_lds[8 * RG_NGRAD1];
 
+// Per-lane gradient partials in LDS, parameter-major ([slot][lane], so a
+// wave's adds hit consecutive doubles): gp[i] += v is one LDS add of the
+// lane's own slot (an atomic, so that the compiler does not keep the slots
+// in registers across the loop; each slot has one writer, so the sum is the
+// same sequence of additions as in registers).
+struct rg_GPRef {
+    double *q;
+    __device__ __forceinline__ void operator+=(double v) const {
+        __hip_atomic_fetch_add(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __device__ __forceinline__ operator double() const { return *q; }
+};
+struct rg_GPLds {
+    double *p;
+    __device__ __forceinline__ rg_GPRef operator[](int i) const { return rg_GPRef{p + i * RG_ADJ_BLOCK}; }
+};
+
 // Discrete adjoint of the RK4 map (exact transpose of one step):
 //   Kb4 = dt/6 lam,            Yb4 = J(Y4)^T Kb4
 //   Kb3 = dt/3 lam + dt Yb4,   Yb3 = J(Y3)^T Kb3
@@ -698,8 +715,9 @@ __shared__ double rg_red_lds[8 * RG_NGRAD1];
 #define RG_ADJ_NS 4
 #endif
 
+template <typename GPT>
 __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, double om, double dt,
-                                                const rg_P &P, double *lam, double *gp, rg_GA &G) {
+                                                const rg_P &P, double *lam, GPT gp, rg_GA &G) {
     const double h2 = 0.5 * dt, dt3 = dt / 3.0, dt6 = dt / 6.0;
     const double tj = sp[(long long)RG_ADJ_NS * RG_NY * SL];
     double Kb[RG_NY], Yb[RG_NY], lsum[RG_NY];
@@ -746,7 +764,8 @@ __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, 
 // in a fixed order (wave shuffles, then waves in order), the spline
 // coefficients from the LDS accumulator; written (add = false) or added to
 // what the workgroup's earlier launches left (add = true).
-__device__ __forceinline__ void rg_write_partials(const rg_kargs &a, const double *gp, rg_GA &G, bool add) {
+template <typename GPT>
+__device__ __forceinline__ void rg_write_partials(const rg_kargs &a, GPT gp, rg_GA &G, bool add) {
 #if RG_NSPLTAB > 0
     for (int k = 0; k < RG_NSPLTAB; k++) G.flush(k);
 #endif
@@ -771,7 +790,13 @@ __device__ __forceinline__ void rg_write_partials(const rg_kargs &a, const doubl
 #endif
 }
 
-extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kargs a) {
+#if RG_GP_LDS
+__shared__ double rg_gp_lds[RG_NGRAD1 * RG_ADJ_BLOCK];
+#define RG_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3, 8)))
+#else
+#define RG_ADJ_OCCUPANCY
+#endif
+extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) RG_ADJ_OCCUPANCY rg_rk4_adjoint(rg_kargs a) {
     rg_stage_tables(a);
 #if RG_NSPLTAB > 0
     for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) rg_spl_grad_lds[i] = 0.0;
@@ -780,8 +805,13 @@ extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_rk4_adjoint(rg_kar
     const rg_P P = rg_params(a);
     rg_GA G;
     G.init();
+#if RG_GP_LDS
+    for (int i = 0; i < RG_NGRAD1; i++) rg_gp_lds[i * RG_ADJ_BLOCK + threadIdx.x] = 0.0;
+    const rg_GPLds gp{rg_gp_lds + threadIdx.x};
+#else
     double gp[RG_NGRAD1];
     for (int i = 0; i < RG_NGRAD1; i++) gp[i] = 0.0;
+#endif
     const long long n = a.n;
     const long long GL = (long long)gridDim.x * blockDim.x;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -104,8 +104,7 @@ static void code_cache_put(uint64_t key, const std::vector<char> &code) {
 // that they are computed once per ray; each such value then stays live in
 // registers across the time loop, which the rolled programs (register
 // bound already) do not afford.
-static void factor_spec(Graph &g, FunctionSpec &spec, bool table_exp, bool hoist) {
-    spec.table_exp = table_exp;
+static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist) {
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);
     for (const SplineSeed &s : spec.spline_seeds) {
@@ -189,13 +188,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     if (p->spl_total > 8192)
         return fail(RG_EUNSUPPORTED, "spline tables larger than 8192 coefficients (LDS staging)");
     // Rolled stage loops (one copy of the right-hand side per kernel loop)
-    // for right-hand sides with many constants; they also stage the adjoint's
-    // stage states in LDS (3 * 2*dim doubles per lane), next to the spline
-    // tables and their gradient accumulator.
+    // for right-hand sides with many constants, unless large spline tables
+    // already fill LDS.
     p->rolled = n_consts > 32 && p->spl_total <= 4096;
-    // The table-driven exponential saves instructions but waits on an LDS
-    // read; the rolled kernels run at 2-3 waves per SIMD, too few to hide
-    // that latency, and keep the library exponential (pure ALU).
 
     // ---- emit rhs and D
     std::ostringstream fs;
@@ -206,7 +201,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "RG_FN void rg_rhs(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, double *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
-        factor_spec(g, spec, !p->rolled, !p->rolled);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_rhs);
     }
     if (opts.fp32) {
@@ -221,7 +216,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P, float *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         Flops fl32;
-        factor_spec(g, spec, !p->rolled, !p->rolled);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl32);
         p->has_f32 = true;
     }
@@ -232,7 +227,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
         spec.returns_value = true;
-        factor_spec(g, spec, !p->rolled, !p->rolled);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
     {
@@ -245,7 +240,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < d; i++)
             spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
         Flops fl_dk;
-        factor_spec(g, spec, !p->rolled, !p->rolled);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_dk);
     }
     p->info.n_nodes_rhs = fl_rhs.ops;
@@ -260,9 +255,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         auto A = [&](uint32_t n) { return adj[n] == NONE ? g.constant(0.0) : adj[n]; };
         FunctionSpec spec;
         spec.signature =
-            "RG_FN void rg_vjp(const double *__restrict__ y, const double om, const double t, "
+            "template <typename GPT>\nRG_FN void rg_vjp(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, const double *__restrict__ av, double *__restrict__ jv, "
-            "double *__restrict__ gp, rg_GA &G) {\n  (void)om; (void)t; (void)P; (void)gp; (void)G;";
+            "GPT gp, rg_GA &G) {\n  (void)om; (void)t; (void)P; (void)gp; (void)G;";
         for (uint32_t j = 0; j < ny; j++) spec.outputs.push_back({A(yv[j]), "jv[" + std::to_string(j) + "]", false});
         std::vector<uint32_t> freach = g.reachable(f);
         for (uint32_t n : freach) {
@@ -278,7 +273,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             const Node &nd = g.node(n);
             if (nd.op == SPLINE) spec.spline_seeds.push_back({n, A(n)});
         }
-        factor_spec(g, spec, !p->rolled, !p->rolled);
+        factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
     }
@@ -288,6 +283,17 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     // hundred issued flops against a global-memory latency the few waves of
     // a small ray batch cannot hide); otherwise they are stored.
     p->adj_recompute = fl_rhs.issued + fl_rhs.inv_issued < 400.0;
+    // With stored stage states the reverse step is a loop around one large
+    // VJP whose registers decide the waves per SIMD: there the per-lane
+    // gradient partials of scalar parameters are accumulated in LDS instead
+    // of registers (one LDS add each per VJP) and the kernel is bounded to
+    // 168 registers (three waves per SIMD), where that LDS and the tables'
+    // still leave room for three workgroups per CU.
+    {
+        const size_t ngrad1 = p->grad_param.empty() ? 1 : p->grad_param.size();
+        const size_t lds = ngrad1 * kAdjointBlock * 8 + (size_t)p->spl_total * 16 + 2048 + 8 * ngrad1 * 8;
+        p->gp_lds = p->has_vjp && !p->adj_recompute && lds <= 53248;
+    }
 
     // ---- configuration header
     std::ostringstream cs;
@@ -298,8 +304,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
        << "\n#define RG_USES_EXP " << (p->functions_src.find("rg_exp(") != std::string::npos ? 1 : 0)
        << "\n#define RG_RHS_ZERO " << zero_mask
        << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_RECOMPUTE "
-       << (p->adj_recompute ? 1 : 0) << "\n#define RG_ADJ_BLOCK " << kAdjointBlock
-       << "\n";
+       << (p->adj_recompute ? 1 : 0) << "\n#define RG_GP_LDS " << (p->gp_lds ? 1 : 0)
+       << "\n#define RG_ADJ_BLOCK " << kAdjointBlock << "\n";
     cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)
        << int_array("rg_spl_len", p->spl_len) << int_array("rg_spl_ny", p->spl_ny)
        << int_array("rg_grad_param", p->grad_param) << int_array("rg_grad_elem", p->grad_elem);

@@ -37,6 +37,7 @@ struct rg_program {
     bool rolled = false;  // RK4 stage loops rolled (RG_ROLL)
     bool has_f32 = false; // single precision RK4 kernel built (RG_HAS_F32)
     bool adj_recompute = false;  // adjoint recomputes stage states (RG_ADJ_RECOMPUTE)
+    bool gp_lds = false;  // adjoint gradient partials in LDS, 3 waves per SIMD (RG_GP_LDS)
     // gradient layout
     std::vector<int> grad_param, grad_elem;       // scalar slots
     std::vector<int> spl_param, spl_off, spl_len, spl_ny;

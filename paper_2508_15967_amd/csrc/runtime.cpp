@@ -414,9 +414,30 @@ static rg_status tune_dopri(rg_program *p, const rg_kargs &a, hipStream_t s, Tun
     if (p->tune.empty()) tune_load(p);
     auto it = p->tune.find(key);
     if (it != p->tune.end()) { *out = it->second; p->last.tuned = 1; return RG_OK; }
+    // The compaction interval pays only where rays finish at different
+    // times, which a sample with capped budgets does not show: a problem
+    // whose trace is short (one run at block 256, interval 8, under 100 ms)
+    // is tuned on itself (its outputs are overwritten by the run that
+    // follows); a longer one on a sixteenth of the rays, budgets capped at
+    // 400 steps.
     rg_kargs t = a;
-    t.n_run = std::min<long long>(a.n, std::max<long long>(65536, a.n / 16));
-    t.budget_cap = 400;
+    {
+        std::vector<Launch> seq;
+        RGCHK(dopri_seq(p, a, 256, 8, seq));
+        hipEvent_t e[2];
+        for (hipEvent_t &x : e) HIPCHK(hipEventCreate(&x));
+        HIPCHK(hipEventRecord(e[0], s));
+        RGCHK(run_seq(p, seq, false, s));
+        HIPCHK(hipEventRecord(e[1], s));
+        HIPCHK(hipEventSynchronize(e[1]));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+        for (hipEvent_t &x : e) (void)hipEventDestroy(x);
+        if (ms > 100.0f) {
+            t.n_run = std::min<long long>(a.n, std::max<long long>(65536, a.n / 16));
+            t.budget_cap = 400;
+        }
+    }
     float best = 1e30f;
     TuneEntry bt;
     for (int block : {64, 128, 256})
