@@ -79,6 +79,7 @@ struct Emitter {
     std::vector<uint32_t> consumer;  // unique consumer of a single-use node
     bool f32 = false;                // emit single precision (float) code
     std::vector<char> inv;           // value depends only on constants, parameters, omega
+    uint32_t inv_state = 0;          // and these state components (constant along a ray)
     bool cur_inv = false;            // the operation being counted is ray-invariant
 
     const char *T() const { return f32 ? "float" : "double"; }
@@ -149,7 +150,7 @@ struct Emitter {
         for (uint32_t n : order) {
             const Node &nd = g.node(n);
             if (nd.op == CONST || nd.op == PARAM) inv[n] = 1;
-            else if (nd.op == VAR) inv[n] = nd.aux / 8 == VK_OMEGA;
+            else if (nd.op == VAR) inv[n] = g.ray_invariant_var(nd, inv_state);
             else inv[n] = (nd.a == NONE || inv[nd.a]) && (nd.b == NONE || inv[nd.b]);
         }
         for (uint32_t n : order) {
@@ -670,6 +671,7 @@ std::string emit_function(const Graph &g, const FunctionSpec &spec,
                           const std::vector<int> &param_table_slot, Flops *flops) {
     Emitter em(g, param_table_slot);
     em.f32 = spec.fp32;
+    em.inv_state = spec.inv_state;
     if (spec.fp32 && !spec.spline_seeds.empty()) throw std::invalid_argument("single precision VJP");
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);

@@ -54,6 +54,7 @@ struct FunctionSpec {
     std::vector<SplineSeed> spline_seeds;  // VJP only
     bool returns_value = false;            // single output via "return"
     bool fp32 = false;                     // single precision (no spline nodes)
+    uint32_t inv_state = 0;                // state components constant along a ray (bit c: y[c])
 };
 
 // Emit a function.  `tables` maps a spline-definition's parameter to a table

@@ -318,7 +318,8 @@ std::vector<uint32_t> Graph::adjoints(const std::vector<uint32_t> &outs,
 
 // ------------------------------------------------------ hoist divisions ---
 
-std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots, bool split_products) {
+std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots, bool split_products,
+                                             uint32_t inv_state) {
     const std::vector<uint32_t> order = reachable(roots);
     const size_t N0 = nodes_.size();
     std::vector<char> inv(N0, 0);
@@ -326,7 +327,7 @@ std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots,
     for (uint32_t n : order) {
         const Node d = nodes_[n];  // copy: factories may grow nodes_
         if (d.op == CONST || d.op == PARAM) inv[n] = 1;
-        else if (d.op == VAR) inv[n] = d.aux / 8 == VK_OMEGA;
+        else if (d.op == VAR) inv[n] = ray_invariant_var(d, inv_state);
         else inv[n] = (d.a == NONE || inv[d.a]) && (d.b == NONE || inv[d.b]);
         if (d.op == CONST || d.op == VAR || d.op == PARAM) {
             nw[n] = n;
@@ -383,7 +384,8 @@ std::vector<uint32_t> Graph::hoist_divisions(const std::vector<uint32_t> &roots,
 
 // ------------------------------------------------------ factor products ---
 
-std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots, bool merge_invariants) {
+std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots, bool merge_invariants,
+                                             uint32_t inv_state) {
     const std::vector<uint32_t> order = reachable(roots);
     const size_t N0 = nodes_.size();
     auto is_prod = [&](uint32_t n) {
@@ -457,7 +459,7 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots,
     std::vector<int> rank(N0, 0);
     for (uint32_t n : order) {
         const Node &d = nodes_[n];
-        if (d.op == VAR) rank[n] = d.aux / 8 == VK_OMEGA ? 1 : 2;
+        if (d.op == VAR) rank[n] = ray_invariant_var(d, inv_state) ? 1 : 2;
         else if (d.op == PARAM) rank[n] = 1;
         else if (d.op != CONST)
             rank[n] = std::max(d.a != NONE ? rank[d.a] : 0, d.b != NONE ? rank[d.b] : 0);

@@ -88,7 +88,11 @@ public:
     // With merge_invariants, a second pairing that first makes the
     // ray-invariant factors of each product one factor is tried, and kept
     // if it needs fewer multiplications per evaluation.
-    std::vector<uint32_t> factor_products(const std::vector<uint32_t> &roots, bool merge_invariants = true);
+    // inv_state: state components (bit c for y[c]) that count as invariant
+    // along a ray besides omega, parameters and constants (components whose
+    // right-hand side is identically zero).
+    std::vector<uint32_t> factor_products(const std::vector<uint32_t> &roots, bool merge_invariants = true,
+                                          uint32_t inv_state = 0);
 
     // The same for sums: every maximal sum (ADD/SUB chains, negations
     // included) is flattened into signed terms, constant terms folded, term
@@ -103,7 +107,18 @@ public:
     // computes once per ray instead of once per evaluation; a variant
     // denominator that is a product with invariant factors I keeps only
     // its variant part V: a / (I V) = (a / V) (1 / I) (with split_products).
-    std::vector<uint32_t> hoist_divisions(const std::vector<uint32_t> &roots, bool split_products = true);
+    std::vector<uint32_t> hoist_divisions(const std::vector<uint32_t> &roots, bool split_products = true,
+                                          uint32_t inv_state = 0);
+
+    // A variable that does not change along a ray: omega, or a state
+    // component whose bit is set in inv_state.
+    bool ray_invariant_var(const Node &d, uint32_t inv_state) const {
+        const int kind = d.aux / 8, i = d.aux % 8;
+        if (kind == VK_OMEGA) return true;
+        if (kind == VK_X) return (inv_state >> i) & 1u;
+        if (kind == VK_K) return (inv_state >> (dim() + i)) & 1u;
+        return false;
+    }
 
     bool is_const(uint32_t n) const { return nodes_[n].op == CONST; }
     bool is_const(uint32_t n, double v) const {

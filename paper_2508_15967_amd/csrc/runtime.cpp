@@ -389,18 +389,29 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     // a shortened run of the real launch, stores included (they write the
     // caller's first snapshots and checkpoints, which the run that follows
     // overwrites): long enough to rank the candidates above timer noise
+    // Candidates in order of preference: among those within 3 % of the
+    // fastest (run-to-run noise), the first is taken, so near-equal
+    // configurations do not flip from one process to the next.
     rg_kargs t = a;
     t.n_steps = std::min(a.n_steps, std::max(128, std::min(1024, a.n_steps / 16)));
-    float best = 1e30f;
-    TuneEntry bt;
-    for (int rpl : {1, 2})
-        for (int block : {64, 128, 256, 512}) {
-            if (fp32 && rpl > 1) continue;
+    const std::pair<int, int> cand[] = {{1, 256}, {1, 512}, {1, 128}, {2, 256}, {2, 128}, {1, 64}, {2, 512}, {2, 64}};
+    std::vector<float> ms_of;
+    for (const auto &c : cand) {
+        float ms = 1e30f;
+        if (!(fp32 && c.first > 1)) {
             std::vector<Launch> seq;
-            RGCHK(persistent_rk4_seq(p, t, block, rpl, seq, fp32));
-            float ms;
+            RGCHK(persistent_rk4_seq(p, t, c.second, c.first, seq, fp32));
             RGCHK(time_seq(p, seq, s, &ms));
-            if (ms < best) { best = ms; bt.block = block; bt.rpl = rpl; }
+        }
+        ms_of.push_back(ms);
+    }
+    const float best = *std::min_element(ms_of.begin(), ms_of.end());
+    TuneEntry bt;
+    for (size_t i = 0; i < ms_of.size(); i++)
+        if (ms_of[i] <= 1.03f * best) {
+            bt.rpl = cand[i].first;
+            bt.block = cand[i].second;
+            break;
         }
     p->tune[key] = bt;
     tune_save(key, bt);
@@ -438,15 +449,24 @@ static rg_status tune_dopri(rg_program *p, const rg_kargs &a, hipStream_t s, Tun
             t.budget_cap = 400;
         }
     }
-    float best = 1e30f;
+    // (preference order and 3 % tolerance as for RK4)
+    const std::pair<int, int> cand[] = {{256, 8}, {128, 8}, {64, 8}, {256, 32}, {128, 32}, {64, 32},
+                                        {256, 128}, {128, 128}, {64, 128}, {256, -1}, {128, -1}, {64, -1}};
+    std::vector<float> ms_of;
+    for (const auto &c : cand) {
+        std::vector<Launch> seq;
+        RGCHK(dopri_seq(p, t, c.first, c.second, seq));
+        float ms;
+        RGCHK(time_seq(p, seq, s, &ms));
+        ms_of.push_back(ms);
+    }
+    const float best = *std::min_element(ms_of.begin(), ms_of.end());
     TuneEntry bt;
-    for (int block : {64, 128, 256})
-        for (int C : {8, 32, 128, -1}) {
-            std::vector<Launch> seq;
-            RGCHK(dopri_seq(p, t, block, C, seq));
-            float ms;
-            RGCHK(time_seq(p, seq, s, &ms));
-            if (ms < best) { best = ms; bt.block = block; bt.compact = C; }
+    for (size_t i = 0; i < ms_of.size(); i++)
+        if (ms_of[i] <= 1.03f * best) {
+            bt.block = cand[i].first;
+            bt.compact = cand[i].second;
+            break;
         }
     p->tune[key] = bt;
     tune_save(key, bt);
