@@ -55,8 +55,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the ray tracer runs on one GPU; --gpus must be 1 "
+                          "(sharding rays over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     from paper_2508_15967_amd import media, raygraph as rgb, workloads as W

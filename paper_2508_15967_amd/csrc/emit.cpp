@@ -520,13 +520,6 @@ struct Emitter {
                 // a unit's phase is at least its inputs'
                 for (size_t i = 0; i < U; i++)
                     for (int c : succ[i]) phase[c] = std::max(phase[c], phase[i]);
-                if (std::getenv("RG_DEBUG_SCHED")) {
-                    std::map<int, int> h;
-                    for (size_t i = 0; i < U; i++) h[phase[i]]++;
-                    std::fprintf(stderr, "phases:");
-                    for (auto &kv : h) std::fprintf(stderr, " %d:%d", kv.first, kv.second);
-                    std::fprintf(stderr, "\n");
-                }
             }
         }
         std::vector<int> when(N, -1);
@@ -534,10 +527,8 @@ struct Emitter {
         std::vector<int> ready;
         for (size_t i = 0; i < U; i++)
             if (unmet[i] == 0) ready.push_back((int)i);
-        int step = 0, live = 0, max_live = 0, cur_phase = 0;
-        bool step_started_new = false;
+        int step = 0, cur_phase = 0;
         while (!ready.empty()) {
-            step_started_new = false;
             // stay in the current phase while it has ready units
             int lowest = 1 << 30;
             for (int r : ready) lowest = std::min(lowest, phase[r]);
@@ -580,29 +571,23 @@ struct Emitter {
                 emit_node(u.node);
                 when[u.node] = step++;
             } else if (u.kind == U_ACC) {
-                step_started_new = !started[u.chain];
                 emit_acc(u.chain, u.leaf);
                 started[u.chain] = 1;
                 when[u.node] = step++;
             } else {
                 emitted[u.node] = 1;
             }
-            for (uint32_t v : u.vals)
-                if (--remaining[v] == 0) live--;
-            if ((u.kind == U_NODE && remaining[u.node] > 0) || (u.kind == U_ACC && step_started_new)) live++;
+            for (uint32_t v : u.vals) --remaining[v];
             if (outs && u.kind != U_ACC && remaining[u.node] > 0)
                 for (size_t oi = 0; oi < outs->size(); oi++)
                     if (!(*out_done)[oi] && (*outs)[oi].node == u.node) {
                         emit_output((*outs)[oi]);
                         (*out_done)[oi] = 1;
-                        if (--remaining[u.node] == 0) live--;
+                        --remaining[u.node];
                     }
-            max_live = std::max(max_live, live);
             for (int sidx : succ[ui])
                 if (--unmet[sidx] == 0) ready.push_back(sidx);
         }
-        if (std::getenv("RG_DEBUG_SCHED"))
-            std::fprintf(stderr, "schedule: %zu units, %zu chains, max live %d\n", U, chains.size(), max_live);
     }
 
     // Gradient scatter of spline coefficients: for each cell group, the 16
