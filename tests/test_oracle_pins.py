@@ -470,3 +470,34 @@ def test_coldplasma_O_mode_follows_eq4_parabola(oracle):
     # the rays turned around (k_x < 0 at T = 40, turning at x = 10)
     assert np.all(r["k"][0] < 0)
     assert max(errs) < 1e-10, errs
+
+
+def test_coldplasma_X_mode_turns_where_RL_over_S_is_ny2(oracle):
+    """X-mode rays of the full cold-plasma D (eqs. 5-10), launched at x = 12
+    toward higher density: with n_y = k_y/w fixed (D does not depend on y)
+    and n_x = 0 at the turning point, they turn where R L / S = n_y^2, just
+    before the L cut-off x = 20.  R, L, S are written out here from the
+    Stix definitions (electrons, |Omega_e| = w/2, X = 0.5 (0.1 x + 1)) and the
+    turning points found by bisection; the oracle's largest x on a fine
+    trajectory must match them."""
+    w = W.coldplasma("X", n_rays=16, x0=12.0, direction=1.0, dt=1e-2, n_steps=6000)
+    w.store_every = 1
+    r = oracle.trace(w, store=True)
+    assert np.all(r["status"] == oracle.RAY_OK)
+    xmax = r["traj"][:, 0].max(axis=0)
+    Y = 0.5
+
+    def g(x, ny2):
+        X = 0.5 * (0.1 * x + 1.0)
+        R, L = 1.0 - X / (1.0 - Y), 1.0 - X / (1.0 + Y)
+        return R * L / (0.5 * (R + L)) - ny2
+
+    for i in range(w.n):
+        ny2 = (w.k0[1, i] / w.omega[i]) ** 2
+        lo, hi = 12.0, 20.0
+        assert g(lo, ny2) > 0 > g(hi, ny2)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if g(mid, ny2) > 0 else (lo, mid)
+        assert abs(xmax[i] - lo) < 1e-4, (i, xmax[i], lo)
+    assert np.all(r["k"][0] < 0)   # turned around
