@@ -254,7 +254,8 @@ typedef struct {
  * stops, see status); DOPRI54 runs until the box is left, the budget is used
  * or t_end is reached.  Requires a program compiled without compile_only.
  * n_rays = 0 returns RG_OK without touching any ray buffer (they may then
- * be NULL). */
+ * be NULL).  No output buffer may overlap an input buffer or another output
+ * (RG_EINVAL): the autotuner's sample runs write the outputs first. */
 rg_status rg_trace_rays(rg_program *p, const rg_trace_desc *d, void *hip_stream);
 
 typedef struct {

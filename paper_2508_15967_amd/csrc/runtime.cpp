@@ -296,6 +296,36 @@ static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
         a.max_steps = d.max_steps;
         a.h0 = d.h0; a.rtol = d.rtol; a.atol = d.atol; a.hmin = d.hmin; a.t_end = d.t_end;
     }
+    // No output may overlap an input or another output: the autotuner's
+    // sample runs write the outputs before the trace reads its inputs.
+    struct Range { const void *p; size_t bytes; const char *name; };
+    const size_t ns = (d.integrator == RG_RK4 && d.store_every > 0) ? (size_t)(d.n_steps / d.store_every + 1) : 0;
+    const size_t nc = (d.integrator == RG_RK4 && d.checkpoint_every > 0)
+                          ? (size_t)((d.n_steps + d.checkpoint_every - 1) / d.checkpoint_every) : 0;
+    const Range in[] = {{d.x0, 8 * dim * n, "x0"}, {d.k0, 8 * dim * n, "k0"}, {d.t0, 8 * n, "t0"},
+                        {d.omega, 8 * n, "omega"},
+                        {d.integrator == RG_DOPRI54 ? d.budget : nullptr, 4 * n, "budget"}};
+    const Range out[] = {{d.x_out, 8 * dim * n, "x_out"}, {d.k_out, 8 * dim * n, "k_out"},
+                         {d.t_out, 8 * n, "t_out"}, {d.status_out, 4 * n, "status_out"},
+                         {d.steps_out, 4 * n, "steps_out"},
+                         {d.integrator == RG_DOPRI54 ? d.attempts_out : nullptr, 4 * n, "attempts_out"},
+                         {ns ? d.traj : nullptr, 8 * ns * 2 * dim * n, "traj"},
+                         {ns ? d.traj_D : nullptr, 8 * ns * n, "traj_D"},
+                         {nc ? d.checkpoints : nullptr, 8 * nc * (2 * dim + 1) * n, "checkpoints"}};
+    auto overlap = [](const Range &u, const Range &v) {
+        if (!u.p || !v.p || !u.bytes || !v.bytes) return false;
+        const char *a0 = (const char *)u.p, *b0 = (const char *)v.p;
+        return a0 < b0 + v.bytes && b0 < a0 + u.bytes;
+    };
+    const size_t n_out = sizeof out / sizeof out[0];
+    for (size_t i = 0; i < n_out; i++) {
+        for (const Range &r : in)
+            if (overlap(out[i], r))
+                return fail(RG_EINVAL, std::string(out[i].name) + " overlaps input " + r.name);
+        for (size_t j = i + 1; j < n_out; j++)
+            if (overlap(out[i], out[j]))
+                return fail(RG_EINVAL, std::string(out[i].name) + " overlaps " + out[j].name);
+    }
     return RG_OK;
 }
 

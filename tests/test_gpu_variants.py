@@ -117,8 +117,8 @@ def test_empty_and_single_ray(oracle):
 
 
 def test_boundary_rejects_bad_buffers():
-    """Host pointers and undersized device buffers are refused before any
-    launch (RG_EINVAL), with a message."""
+    """Host pointers, undersized device buffers and overlapping outputs are
+    refused before any launch (RG_EINVAL), with a message."""
     torch = U.torch_mod()
     w = W.make("1", 128)
     _, _, prog, _ = U.program(w)
@@ -143,6 +143,13 @@ def test_boundary_rejects_bad_buffers():
     d = prog.make_desc(x0, k0, om, dt=1e-3, n_steps=10, x_out=xo, k_out=ko, block=96)
     with pytest.raises(rgb.RayGraphError):
         prog.trace_desc(d)
+    # outputs may not overlap inputs or each other (the autotuner's sample
+    # runs write the outputs before the trace reads its inputs)
+    for xo2, ko2, what in ((x0, ko, "overlaps input x0"), (xo, xo, "overlaps k_out")):
+        d = prog.make_desc(x0, k0, om, dt=1e-3, n_steps=10, x_out=xo2, k_out=ko2)
+        with pytest.raises(rgb.RayGraphError) as e:
+            prog.trace_desc(d)
+        assert e.value.status == rgb.RG_EINVAL and what in str(e.value), str(e.value)
 
 
 @pytest.mark.parametrize("cfg,n,steps", [("4", 1000, 300), ("5", 300, 300)])
