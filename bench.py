@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--traffic", default="",
                     help="HBM-traffic summary (default: profiles/traffic_<kernel>_<workload>.txt)")
+    ap.add_argument("--rays", type=int, default=0, help="trace only the first N rays of the workload (0 = all)")
     ap.add_argument("--block", type=int, default=0, help="fix the block size (0 = autotuned)")
     ap.add_argument("--rpl", type=int, default=0, help="fix rays per lane (0 = autotuned)")
     ap.add_argument("--compact", type=int, default=0, help="fix the compaction interval (0 = autotuned)")
@@ -62,6 +63,9 @@ def main():
     from paper_2508_15967_amd import media, raygraph as rgb, workloads as W
 
     w = W.make(args.config)
+    full_size = not (0 < args.rays < w.n)
+    if not full_size:
+        w = w.subset(args.rays)
     adjoint = args.config in ("4", "5")
     dev = torch.device("cuda:0")
     g, D, params = media.build(w.medium)
@@ -202,7 +206,7 @@ def main():
     # only for the source they were taken on
     traffic = None
     tfile = args.traffic or os.path.join(ROOT, "profiles", f"traffic_{kname}_{w.name}.txt")
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and full_size:
         kv = {}
         for line in open(tfile):
             if ":" in line and not line.startswith("#"):
@@ -220,7 +224,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_rays": n, "integrator": "RK4" if w.integrator == W.RK4 else "DOPRI54",
                    "n_steps": w.n_steps, "dt": w.dt, "store_every": w.store_every,
-                   "ray_steps_per_trace": ray_steps, "adjoint": adjoint},
+                   "ray_steps_per_trace": ray_steps, "adjoint": adjoint,
+                   **({"attempts_per_trace": attempts} if w.integrator == W.DOPRI54 else {})},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": kname, "kernel_ms": kernel_ms,
