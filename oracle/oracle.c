@@ -593,13 +593,24 @@ static const double DP_B4[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 /
 
 /* Step-size factor after an attempt with scaled error err:
  * 0.9 err^(-1/5), rounded down to a multiple of 1/32, clipped to
- * [0.2, facmax].  The rounding makes the next step size an exactly
- * reproducible function of err away from the rounding points. */
+ * [0.2, facmax].  That is k/32 with k the largest integer such that
+ * k <= 28.8 err^(-1/5), i.e. such that err (5k)^5 <= 144^5 (28.8 = 144/5).
+ * The inequality is decided here as written: (5k)^5 and 144^5 are integers
+ * below 2^53, exact in double, so the only rounding is the product
+ * err * (5k)^5, and no transcendental function takes part; the next step
+ * size is an exactly reproducible function of err.  k is found by counting
+ * up (k <= 161 is enough: 161/32 exceeds the largest factor, 5). */
 static double dp_factor(double err, double facmax)
 {
-    double fac = 0.9 * pow(err, -0.2);
-    fac = floor(32.0 * fac) / 32.0;
-    if (!(fac >= 0.2)) fac = 0.2; /* also catches NaN */
+    const double lim = 61917364224.0; /* 144^5 */
+    int k = 0;
+    while (k < 161) {
+        const double c = 5.0 * (k + 1);
+        if (!(err * (c * c * c * c * c) <= lim)) break; /* also stops at NaN */
+        k++;
+    }
+    double fac = k / 32.0;
+    if (!(fac >= 0.2)) fac = 0.2;
     if (fac > facmax) fac = facmax;
     return fac;
 }
@@ -673,6 +684,8 @@ static void set_threads(int nt)
     (void)nt;
 #endif
 }
+
+double om_dp_factor(double err, double facmax) { return dp_factor(err, facmax); }
 
 int om_threads(void)
 {

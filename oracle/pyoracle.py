@@ -63,6 +63,8 @@ def lib():
         _lib.om_param_vjp_points.restype = C.c_int
         _lib.om_n_params.restype = C.c_int64
         _lib.om_threads.restype = C.c_int
+        _lib.om_dp_factor.restype = C.c_double
+        _lib.om_dp_factor.argtypes = [C.c_double, C.c_double]
     return _lib
 
 
@@ -212,6 +214,11 @@ def adjoint(w, lam_end, n_threads: int = 0):
 
 def threads() -> int:
     return int(lib().om_threads())
+
+
+def dp_factor(err: float, facmax: float = 5.0) -> float:
+    """The Dormand-Prince step-size factor after an attempt with scaled error err."""
+    return float(lib().om_dp_factor(float(err), float(facmax)))
 
 
 def dopri_tableau():

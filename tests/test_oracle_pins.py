@@ -501,3 +501,37 @@ def test_coldplasma_X_mode_turns_where_RL_over_S_is_ny2(oracle):
             lo, hi = (mid, hi) if g(mid, ny2) > 0 else (lo, mid)
         assert abs(xmax[i] - lo) < 1e-4, (i, xmax[i], lo)
     assert np.all(r["k"][0] < 0)   # turned around
+
+
+def test_dopri_step_factor_definition(oracle):
+    """The Dormand-Prince step factor is 0.9 err^(-1/5) rounded down to a
+    multiple of 1/32 and clipped to [0.2, facmax]: checked against that
+    definition evaluated in 50-digit decimal arithmetic (an independent
+    route: a decimal power, not the oracle's integer inequality), for
+    random errors over 1e-12..1e6 and for errors at and one ulp around every
+    rounding point err = (28.8/k)^5, where only the rounding of one product
+    may move the result by one step of 1/32."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+
+    def exact(err, facmax):
+        if err == 0.0:
+            return facmax
+        fac = (Decimal("28.8") * Decimal(err) ** Decimal("-0.2")).to_integral_value(rounding="ROUND_FLOOR")
+        fac = float(fac) / 32.0
+        return min(max(fac, 0.2), facmax)
+
+    rng = np.random.default_rng(5)
+    errs = list(10.0 ** rng.uniform(-12, 6, 4000)) + [0.0, 1.0, 1e-300, 1e300]
+    for e in errs:
+        for fm in (5.0, 1.0):
+            assert oracle.dp_factor(e, fm) == exact(e, fm), (e, fm)
+    assert oracle.dp_factor(float("inf"), 1.0) == 0.2 and oracle.dp_factor(float("nan"), 5.0) == 0.2
+    for k in range(1, 162):
+        t = (28.8 / k) ** 5
+        for e in (np.nextafter(t, 0.0), t, np.nextafter(t, np.inf)):
+            got, want = oracle.dp_factor(e, 5.0), exact(e, 5.0)
+            assert got == want or abs(got - want) == 1.0 / 32.0, (k, e, got, want)
+        # a few ulp away from the rounding point the decision is exact
+        for e in (t * (1 - 8 * 2.0 ** -52), t * (1 + 8 * 2.0 ** -52)):
+            assert oracle.dp_factor(e, 5.0) == exact(e, 5.0), (k, e)
