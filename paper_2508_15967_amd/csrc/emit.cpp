@@ -22,10 +22,9 @@ const IssuedWeights &issued_weights() {
     //   sqrt: 7 fma + 2 mul + rsq         = 17
     //   log: 14 fma + 43 add + 7 mul + rcp = 79
     //   sin/cos: 24 fma + 56 add + 11 mul = 115
-    //   pow: 42 fma + 70 add + 11 mul + rcp = 166
     //   rg_rcp (reciprocal, rcp + two Newton steps): rcp + 4 fma = 9
     static const IssuedWeights w{/*div*/ 14.0, /*exp*/ 14.0, /*log*/ 79.0, /*sqrt*/ 17.0,
-                                 /*sincos*/ 115.0, /*pow*/ 166.0, /*rcp*/ 9.0};
+                                 /*sincos*/ 115.0, /*rcp*/ 9.0};
     return w;
 }
 

@@ -30,7 +30,7 @@ struct Flops {
 // (fma counted as 2, add/mul as 1; compares, selects, integer and exponent
 // manipulation count 0).
 struct IssuedWeights {
-    double div, exp, log, sqrt, sincos, pow, rcp;
+    double div, exp, log, sqrt, sincos, rcp;
 };
 const IssuedWeights &issued_weights();
 

@@ -387,9 +387,24 @@ extern "C" __global__ void __launch_bounds__(512) rg_plain_finish(rg_kargs a) {
 // Step factor 0.9 err^(-1/5) rounded down to a multiple of 1/32 and clipped
 // to [0.2, facmax]; the rounding makes the next step an exactly
 // reproducible function of err except at the rounding points.
+// Step-size factor: 0.9 err^(-1/5) rounded down to a multiple of 1/32 and
+// clipped to [0.2, facmax], i.e. k/32 with k the largest integer such that
+// err (5k)^5 <= 144^5 (28.8 = 144/5; (5k)^5 and 144^5 are exact in double,
+// so the inequality is decided with one rounded product and no
+// transcendental).  A single-precision estimate of 28.8 err^(-1/5)
+// (hardware log2 and exp2, relative error about 1e-6, so within one of k for
+// k <= 161) is corrected by testing the inequality one step up and one step
+// down: a few dozen instructions instead of a double-precision pow.
+__device__ __forceinline__ bool rg_dp_fac_ok(double err, int k) {
+    const double c = 5.0 * k;
+    return err * (c * c * c * c * c) <= 61917364224.0;  // 144^5
+}
 __device__ __forceinline__ double rg_dp_factor(double err, double facmax) {
-    double fac = 0.9 * pow(err, -0.2);
-    fac = floor(32.0 * fac) / 32.0;
+    const float g = 28.8f * exp2f(-0.2f * log2f((float)err));
+    int k = (int)fminf(fmaxf(floorf(g), 0.0f), 161.0f);  // NaN -> 0
+    if (k < 161 && rg_dp_fac_ok(err, k + 1)) k++;
+    if (k > 0 && !rg_dp_fac_ok(err, k)) k--;
+    double fac = k / 32.0;
     if (!(fac >= 0.2)) fac = 0.2;
     if (fac > facmax) fac = facmax;
     return fac;

@@ -346,9 +346,10 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     const double dp = 64.0 * ny + 8.0;
     const IssuedWeights &w = issued_weights();
     I.dopri_attempt_flops_alg = 6 * fl_rhs_dp.alg + dp;
-    // (sqrt, the division by the scale per component and the pow of the
-    // step factor counted at their issued weights)
-    I.dopri_attempt_flops_issued = 6 * fl_rhs_dp.issued + dp - 3.0 - ny + w.sqrt + ny * w.div + w.pow;
+    // (sqrt and the division by the scale per component counted at their
+    // issued weights; the step factor is a single-precision estimate and two
+    // exact tests of five FP64 multiplications each: 10)
+    I.dopri_attempt_flops_issued = 6 * fl_rhs_dp.issued + dp - 3.0 - ny + w.sqrt + ny * w.div + 10.0;
     if (p->has_vjp) {
         I.vjp_flops_alg = fl_vjp.alg;
         I.vjp_flops_issued = fl_vjp.issued;
