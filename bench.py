@@ -204,17 +204,25 @@ def main():
     # HBM bytes per launch of that kernel from the rocprofv3 FETCH_SIZE and
     # WRITE_SIZE passes (calibrated against a copy of known size), valid
     # only for the source they were taken on
-    traffic = None
-    tfile = args.traffic or os.path.join(ROOT, "profiles", f"traffic_{kname}_{w.name}.txt")
-    if os.path.exists(tfile) and full_size:
+    def profile_entry(path):
+        """key: value pairs of a committed counter summary, if it was taken on
+        this kernel, workload and generated source"""
+        if not (os.path.exists(path) and full_size):
+            return None
         kv = {}
-        for line in open(tfile):
+        for line in open(path):
             if ":" in line and not line.startswith("#"):
                 key, val = line.split(":", 1)
                 kv[key.strip()] = val.strip()
-        if (kv.get("source_hash") == "%016x" % info["source_hash"] and kv.get("kernel") == kname
-                and kv.get("workload") == w.name):
-            traffic = float(kv["hbm_bytes_per_launch"])
+        ok = (kv.get("source_hash") == "%016x" % info["source_hash"] and kv.get("kernel") == kname
+              and kv.get("workload") == w.name)
+        return kv if ok else None
+
+    tkv = profile_entry(args.traffic or os.path.join(ROOT, "profiles", f"traffic_{kname}_{w.name}.txt"))
+    traffic = float(tkv["hbm_bytes_per_launch"]) if tkv else None
+    # FP64 flops per ray-step counted by the hardware (SQ_INSTS_VALU_FLOPS_FP64)
+    fkv = profile_entry(os.path.join(ROOT, "profiles", f"fp64_{kname}_{w.name}.txt"))
+    hw_flops = float(fkv["fp64_flops_per_ray_step"]) if fkv else None
 
     result = {
         "metric": ("FP64 ray-steps/s (persistent fused RK4, one launch per trace)" if w.integrator == W.RK4 else
@@ -230,7 +238,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": kname, "kernel_ms": kernel_ms,
                      "flops_per_ray_step_alg": k_alg / max(ray_steps, 1),
-                     "achieved_issued": achieved_iss, "frac_issued": achieved_iss / PEAK_FP64_TFLOPS},
+                     "achieved_issued": achieved_iss, "frac_issued": achieved_iss / PEAK_FP64_TFLOPS,
+                     "hw_fp64_flops_per_ray_step": hw_flops,
+                     "frac_hw": (hw_flops * ray_steps / (kernel_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+                                 if hw_flops else None)},
         "launch": launch, "compile_s": compile_s, "warmup_s": warm_s,
         "source_hash": "%016x" % info["source_hash"],
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
