@@ -62,6 +62,7 @@ struct Emitter {
         std::vector<uint32_t> nodes;
         int maxdu = 0, maxdv = 0;
         bool emitted = false;
+        int rows_done = 0;  // bit dv: row sums for order dv in v emitted
     };
     std::vector<Group> groups;
     // Chains of single-use additions/subtractions become accumulations whose
@@ -209,7 +210,7 @@ struct Emitter {
                 for (size_t i = 0; i < groups.size(); i++)
                     if (groups[i].def == def && groups[i].u == nd.a && groups[i].v == nd.b) gi = (int)i;
                 if (gi < 0) {
-                    groups.push_back(Group{def, nd.a, nd.b, {}, 0, 0, false});
+                    groups.push_back(Group{def, nd.a, nd.b, {}, 0, 0, false, 0});
                     gi = (int)groups.size() - 1;
                 }
                 groups[gi].nodes.push_back(n);
@@ -278,10 +279,18 @@ struct Emitter {
             int gi = group_of.at(n);
             emit_group_head(gi);
             std::string G = "s" + std::to_string(gi);
+            const int dv = nd.aux % 4;
+            if (!(groups[gi].rows_done & (1 << dv))) {
+                // row sums for this order in v, shared by the group's nodes
+                groups[gi].rows_done |= 1 << dv;
+                os << "  double " << G << "q" << dv << "[4]; rg_bs_rows(" << G << "c, " << G << "wy" << dv << ", "
+                   << G << "q" << dv << ");\n";
+                count_plain(28);
+            }
             std::string sc = spline_scale(n);
-            os << "  const double " << name(n) << " = " << (sc.empty() ? "" : sc + " * ") << "rg_bs_dot("
-               << G << "c, " << G << "wx" << nd.aux / 4 << ", " << G << "wy" << nd.aux % 4 << ");\n";
-            count_plain(35 + (sc.empty() ? 0 : 1));
+            os << "  const double " << name(n) << " = " << (sc.empty() ? "" : sc + " * ") << "rg_bs_comb(" << G << "q"
+               << dv << ", " << G << "wx" << nd.aux / 4 << ");\n";
+            count_plain(7 + (sc.empty() ? 0 : 1));
             return;
         }
         default: break;

@@ -200,10 +200,14 @@ RG_FN void rg_bs_w3(double u, double *w) {
     w[0] = -1.0; w[1] = 3.0; w[2] = -3.0; w[3] = 1.0;
 }
 
-// sum_a wx[a] sum_b c[4a+b] wy[b]   35 flops
-RG_FN double rg_bs_dot(const double *c, const double *wx, const double *wy) {
-    double r[4];
+// Tensor-product evaluation sum_a wx[a] sum_b c[4a+b] wy[b] in two parts:
+// the row sums r[a] = sum_b c[4a+b] wy[b] (28 flops), shared by every
+// derivative with the same order in v, and their combination with the
+// weights in u (7 flops).
+RG_FN void rg_bs_rows(const double *c, const double *wy, double *r) {
     for (int a = 0; a < 4; a++)
         r[a] = fma(c[4 * a + 3], wy[3], fma(c[4 * a + 2], wy[2], fma(c[4 * a + 1], wy[1], c[4 * a] * wy[0])));
+}
+RG_FN double rg_bs_comb(const double *r, const double *wx) {
     return fma(r[3], wx[3], fma(r[2], wx[2], fma(r[1], wx[1], r[0] * wx[0])));
 }

@@ -201,7 +201,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
 
     // ---- emit rhs and D
     std::ostringstream fs;
-    Flops fl_rhs, fl_rhs_dp, fl_D, fl_vjp;
+    Flops fl_rhs, fl_rhs_dp, fl_D, fl_vjp, fl_rhs_vjp;
     {
         FunctionSpec spec;
         spec.signature =
@@ -288,9 +288,15 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             const Node &nd = g.node(n);
             if (nd.op == SPLINE) spec.spline_seeds.push_back({n, A(n)});
         }
+        // (for the flop count only) the VJP and the right-hand side at the
+        // same state as one function: the work the two share counts once
+        FunctionSpec both = spec;
+        for (uint32_t i = 0; i < ny; i++) both.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         factor_spec(g, spec, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
+        factor_spec(g, both, !p->rolled);
+        emit_function(g, both, table_slot, &fl_rhs_vjp);
     }
     p->functions_src = fs.str();
     // The adjoint recomputes the stage states Y2..Y4 where three right-hand
@@ -355,11 +361,13 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         I.vjp_flops_issued = fl_vjp.issued;
         I.vjp_flops_ray_invariant = fl_vjp.inv_alg;
         // reverse of one step: recompute (one RK4 step) [+ 3 stage RHS and
-        // 3 stage fma when the stages are recomputed] + 4 VJP + recurrence
-        // (per component: 3 fma, 3 add, 1 mul, 1 add = 12 flops)
+        // 3 stage fma when the stages are recomputed; three of the four VJPs
+        // then run at states whose right-hand side the step evaluates, and
+        // what the two share counts once] + 4 VJP + recurrence (per
+        // component: 3 fma, 3 add, 1 mul, 1 add = 12 flops)
         const double rec = 12.0 * ny;
-        const double st_alg = p->adj_recompute ? 3 * fl_rhs.alg + 6.0 * ny : 0.0;
-        const double st_iss = p->adj_recompute ? 3 * fl_rhs.issued + 6.0 * ny : 0.0;
+        const double st_alg = p->adj_recompute ? 3 * (fl_rhs_vjp.alg - fl_vjp.alg) + 6.0 * ny : 0.0;
+        const double st_iss = p->adj_recompute ? 3 * (fl_rhs_vjp.issued - fl_vjp.issued) + 6.0 * ny : 0.0;
         I.adj_step_flops_alg = I.rk4_step_flops_alg + st_alg + 4 * fl_vjp.alg + rec;
         I.adj_step_flops_issued = I.rk4_step_flops_issued + st_iss + 4 * fl_vjp.issued + rec;
     }
