@@ -475,15 +475,13 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots,
         std::vector<std::pair<uint32_t, uint32_t>> pairs;
         std::vector<Prod> prods;
     };
-    auto srank_of = [&](const Pairing &R) {
-        std::function<int(uint32_t)> f = [&R, &f, &leaf_rank](uint32_t s2) -> int {
-            if (s2 & kVirtual) {
-                const auto &pr = R.pairs[s2 & ~kVirtual];
-                return std::max(f(pr.first), f(pr.second));
-            }
-            return leaf_rank(s2);
-        };
-        return f;
+    // rank of a symbol of a pairing (a pair ranks as its higher side)
+    std::function<int(const Pairing &, uint32_t)> srank_in = [&](const Pairing &R, uint32_t s2) -> int {
+        if (s2 & kVirtual) {
+            const auto &pr = R.pairs[s2 & ~kVirtual];
+            return std::max(srank_in(R, pr.first), srank_in(R, pr.second));
+        }
+        return leaf_rank(s2);
     };
     auto run_pairing = [&](bool merge) {
         Pairing R{{}, prods};
@@ -545,7 +543,7 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots,
     // invariant, the k - 1 among the invariant ones are hoisted; a formed
     // pair costs one if either side varies
     auto per_eval_muls = [&](const Pairing &R) {
-        auto sr = srank_of(R);
+        auto sr = [&](uint32_t s2) { return srank_in(R, s2); };
         size_t c = 0;
         std::set<uint32_t> used;
         std::function<void(uint32_t)> mark = [&](uint32_t s2) {
