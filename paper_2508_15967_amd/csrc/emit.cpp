@@ -78,6 +78,7 @@ struct Emitter {
     std::vector<char> interior;      // node folded into a chain
     std::vector<uint32_t> consumer;  // unique consumer of a single-use node
     bool f32 = false;                // emit single precision (float) code
+    std::vector<signed char> sgn;    // 1: value >= 0, -1: <= 0 (or NaN), 0: not known
     std::vector<char> inv;           // value depends only on constants, parameters, omega
     uint32_t inv_state = 0;          // and these state components (constant along a ray)
     bool cur_inv = false;            // the operation being counted is ray-invariant
@@ -146,6 +147,26 @@ struct Emitter {
     }
 
     void plan(const std::vector<uint32_t> &order, const std::vector<uint32_t> &roots) {
+        // signs the graph fixes (rounding keeps the sign of each of these
+        // operations; NaN may appear wherever a sign is claimed)
+        sgn.assign(g.size(), 0);
+        for (uint32_t n : order) {
+            const Node &nd = g.node(n);
+            auto S = [&](uint32_t m) { return m == NONE ? 0 : (int)sgn[m]; };
+            int s = 0;
+            switch (nd.op) {
+            case CONST: s = nd.val >= 0.0 ? 1 : nd.val <= 0.0 ? -1 : 0; break;
+            case EXP: case SQRT: s = 1; break;
+            case NEG: s = -S(nd.a); break;
+            case POWI: s = nd.aux % 2 == 0 ? 1 : S(nd.a); break;
+            case MUL: s = nd.a == nd.b ? 1 : S(nd.a) * S(nd.b); break;
+            case DIV: s = S(nd.a) * S(nd.b); break;
+            case ADD: s = S(nd.a) == S(nd.b) ? S(nd.a) : 0; break;
+            case SUB: s = S(nd.a) == -S(nd.b) ? S(nd.a) : 0; break;
+            default: break;
+            }
+            sgn[n] = (signed char)s;
+        }
         inv.assign(g.size(), 0);
         for (uint32_t n : order) {
             const Node &nd = g.node(n);
@@ -327,7 +348,12 @@ struct Emitter {
             }
             break;
         case NEG: e = "-" + A; break;
-        case EXP: e = (f32 ? "expf(" : "rg_exp(") + A + ")"; count(EXP); break;
+        case EXP:
+            // the argument proved non-positive (a Gaussian's exponent, say):
+            // the variant without the upper clamp
+            e = (f32 ? "expf(" : sgn[nd.a] < 0 ? "rg_exp_np(" : "rg_exp(") + A + ")";
+            count(EXP);
+            break;
         case LOG: e = fn("log") + "(" + A + ")"; count(LOG); break;
         case SQRT: e = fn("sqrt") + "(" + A + ")"; count(SQRT); break;
         case SIN: e = fn("sin") + "(" + A + ")"; count(SIN); break;

@@ -114,6 +114,10 @@ RG_FN double rg_rcp(double d) {
     0x1.fa7c1819e90d8p+0, 0x1.fbdba3692d514p+0, 0x1.fd3c22b8f71f1p+0, 0x1.fe9d96b2a23d9p+0
 // RG_EXP_TABLE end
 
+// kNonPos: the caller guarantees x <= 0 or NaN (the emitter proves it from
+// the graph), so the upper clamp, whose only role is to keep n in range for
+// x > 1100, is left out (one instruction).
+template <bool kNonPos>
 RG_FN double rg_exp_tab(double x, const double *tab) {
     // below -1100 the result is 0 (a select keeps NaN); above 1100 n stays
     // bounded while r grows with x, so the result overflows to +inf, and a
@@ -122,7 +126,7 @@ RG_FN double rg_exp_tab(double x, const double *tab) {
     // n = x N/ln2 rounded to nearest (even) by adding 1.5 2^52, whose ulp is
     // 1: the sum holds n in its low 32 bits (two's complement), and
     // subtracting the constant again gives n as a double
-    const double s = fma(fmin(x, 1100.0), RG_EXP_INV_L, 0x1.8p52);
+    const double s = fma(kNonPos ? x : fmin(x, 1100.0), RG_EXP_INV_L, 0x1.8p52);
     const double n = s - 0x1.8p52;
     double r = fma(-n, RG_EXP_L1, x);
     r = fma(-n, RG_EXP_L2, r);
@@ -138,10 +142,12 @@ RG_FN double rg_exp_tab(double x, const double *tab) {
 #if defined(__HIPCC__) || defined(__HIPCC_RTC__)
 // the table lives in LDS; every kernel that calls rg_exp stages it first
 __shared__ double rg_exp_lds[RG_EXP_N];
-RG_FN double rg_exp(double x) { return rg_exp_tab(x, rg_exp_lds); }
+RG_FN double rg_exp(double x) { return rg_exp_tab<false>(x, rg_exp_lds); }
+RG_FN double rg_exp_np(double x) { return rg_exp_tab<true>(x, rg_exp_lds); }
 #else
 static const double rg_exp_host_tab[RG_EXP_N] = {RG_EXP_TABLE_VALUES};
-RG_FN double rg_exp(double x) { return rg_exp_tab(x, rg_exp_host_tab); }
+RG_FN double rg_exp(double x) { return rg_exp_tab<false>(x, rg_exp_host_tab); }
+RG_FN double rg_exp_np(double x) { return rg_exp_tab<true>(x, rg_exp_host_tab); }
 #endif
 
 // Single precision reciprocal: the hardware estimate and one Newton step

@@ -322,7 +322,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
        << p->n_params << "\n#define RG_NGRAD " << p->grad_param.size() << "\n#define RG_NSPLTAB "
        << p->spl_param.size() << "\n#define RG_SPL_TOTAL " << (p->spl_total ? p->spl_total : 1)
        << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_HAS_F32 " << (p->has_f32 ? 1 : 0)
-       << "\n#define RG_USES_EXP " << (p->functions_src.find("rg_exp(") != std::string::npos ? 1 : 0)
+       << "\n#define RG_USES_EXP " << (p->functions_src.find("rg_exp") != std::string::npos ? 1 : 0)
        << "\n#define RG_RHS_ZERO " << zero_mask
        << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_RECOMPUTE "
        << (p->adj_recompute ? 1 : 0) << "\n#define RG_GP_LDS " << (p->gp_lds ? 1 : 0)

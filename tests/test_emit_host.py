@@ -264,3 +264,55 @@ def test_ray_invariant_flops_counted_apart():
         counts.append((info["rhs_flops_alg"], info["rhs_flops_ray_invariant"]))
     assert len({c[0] for c in counts}) == 1, counts
     assert all(c[1] > counts[0][1] for c in counts[1:]), counts
+
+
+def test_exp_of_nonpositive_argument():
+    """An exponential whose argument the graph proves non-positive (here
+    -x0^2, -(x0^2 + x1^2)/3) is emitted as the variant without the upper
+    clamp, others (x0, x0^2, -omega x0^2 with omega of unknown sign) as the
+    general one; the variant is within 1.5 ulp of the correctly rounded
+    e^(-x0^2) and exact at the special values."""
+    from paper_2508_15967_amd import raygraph as rgb
+
+    def src(expr_of):
+        g = rgb.Graph(2)
+        x, y = g.x(0), g.x(1)
+        return g.compile(g.omega * expr_of(g, x, y), compile_only=True).functions()
+
+    assert "rg_exp_np(" in src(lambda g, x, y: (-(x * x)).exp())
+    assert "rg_exp_np(" in src(lambda g, x, y: (-(x * x + y * y) / 3.0).exp())
+    for f in (lambda g, x, y: x.exp(), lambda g, x, y: (x * x).exp(),
+              lambda g, x, y: (-(g.omega * x * x)).exp()):
+        s = src(f)
+        assert "rg_exp(" in s and "rg_exp_np(" not in s
+
+    g = rgb.Graph(2)
+    D = g.omega * (-(g.x(0) * g.x(0))).exp()
+    prog = g.compile(D, compile_only=True)
+    rng = np.random.default_rng(23)
+    x = np.concatenate([rng.uniform(0.0, 28.0, 4000), rng.uniform(0.0, 1.0, 2000),
+                        rng.uniform(-5.0, 5.0, 2000)])
+    special = np.array([0.0, -0.0, 27.3, 33.4, 40.0, 1e200, np.inf, -np.inf, np.nan])
+    xs = np.concatenate([x, special])
+    n = xs.size
+    y = np.zeros((4, n))
+    y[0] = xs
+    y[2] = 1.0
+    om = np.ones(n)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, False, tmp)
+        f = np.zeros((4, n))
+        Dv = np.zeros(n)
+        lib.host_eval(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), _ptrs([]),
+                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+    with np.errstate(over="ignore", invalid="ignore"):
+        arg = -(xs * xs)   # the emitted argument: one rounded product, negated
+    ref = _exp_reference(arg[:x.size])
+    assert _exp_ulps(Dv[:x.size], ref).max() <= 1.5
+    got_sp = Dv[x.size:]
+    with np.errstate(over="ignore", invalid="ignore"):
+        ref_sp = np.exp(arg[x.size:])
+    same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
+    fin = np.isfinite(ref_sp) & (ref_sp > 0)
+    same |= fin & (_exp_ulps(got_sp, ref_sp) <= 1.5)
+    assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
