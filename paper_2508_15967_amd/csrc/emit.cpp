@@ -148,8 +148,18 @@ struct Emitter {
 
     void plan(const std::vector<uint32_t> &order, const std::vector<uint32_t> &roots) {
         // signs the graph fixes (rounding keeps the sign of each of these
-        // operations; NaN may appear wherever a sign is claimed)
+        // operations; NaN may appear wherever a sign is claimed).  A zero
+        // counts as either sign, but a zero of the other sign in a divisor
+        // flips the sign of the quotient (1/-0 = -inf, and sqrt(-0) = -0),
+        // so a quotient's sign is claimed only when its divisor cannot be
+        // a zero of the wrong sign: an exponential, an even power, a square
+        // or a nonzero constant.
         sgn.assign(g.size(), 0);
+        auto zero_safe = [&](uint32_t m) {
+            const Node &d = g.node(m);
+            return d.op == EXP || (d.op == CONST && d.val != 0.0) ||
+                   (d.op == POWI && d.aux % 2 == 0) || (d.op == MUL && d.a == d.b);
+        };
         for (uint32_t n : order) {
             const Node &nd = g.node(n);
             auto S = [&](uint32_t m) { return m == NONE ? 0 : (int)sgn[m]; };
@@ -158,9 +168,11 @@ struct Emitter {
             case CONST: s = nd.val >= 0.0 ? 1 : nd.val <= 0.0 ? -1 : 0; break;
             case EXP: case SQRT: s = 1; break;
             case NEG: s = -S(nd.a); break;
-            case POWI: s = nd.aux % 2 == 0 ? 1 : S(nd.a); break;
+            case POWI:
+                s = nd.aux % 2 == 0 ? 1 : (nd.aux > 0 || zero_safe(nd.a)) ? S(nd.a) : 0;
+                break;
             case MUL: s = nd.a == nd.b ? 1 : S(nd.a) * S(nd.b); break;
-            case DIV: s = S(nd.a) * S(nd.b); break;
+            case DIV: s = zero_safe(nd.b) ? S(nd.a) * S(nd.b) : 0; break;
             case ADD: s = S(nd.a) == S(nd.b) ? S(nd.a) : 0; break;
             case SUB: s = S(nd.a) == -S(nd.b) ? S(nd.a) : 0; break;
             default: break;

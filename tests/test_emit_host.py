@@ -316,3 +316,41 @@ def test_exp_of_nonpositive_argument():
     fin = np.isfinite(ref_sp) & (ref_sp > 0)
     same |= fin & (_exp_ulps(got_sp, ref_sp) <= 1.5)
     assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+
+
+def test_exp_sign_proof_respects_signed_zero_divisors():
+    """A quotient's sign is claimed only where its divisor cannot be a zero
+    of the other sign: -1/sqrt(x0) at x0 = -0 is 1/(-0) negated, +inf, so
+    its exponential keeps the overflow clamp and gives +inf (the variant
+    without the clamp would give NaN there).  Divisors that are
+    exponentials, squares or even powers keep the proof."""
+    from paper_2508_15967_amd import raygraph as rgb
+
+    def build(expr_of):
+        g = rgb.Graph(2)
+        return g.compile(g.omega * expr_of(g.x(0), g.x(1)), compile_only=True)
+
+    for f in (lambda x, y: (-(x * x) / y.exp()).exp(),
+              lambda x, y: (-(x * x) / (y * y)).exp(),
+              lambda x, y: (-(x * x) * (y ** -2)).exp()):
+        assert "rg_exp_np(" in build(f).functions()
+    for f in (lambda x, y: (-(1.0 / x.sqrt())).exp(),
+              lambda x, y: (-(x * x) / y.sqrt()).exp(),
+              lambda x, y: (-(y.sqrt() ** -1)).exp()):
+        s = build(f).functions()
+        assert "rg_exp(" in s and "rg_exp_np(" not in s
+
+    prog = build(lambda x, y: (-(1.0 / x.sqrt())).exp())
+    n = 3
+    y = np.zeros((4, n))
+    y[0] = [-0.0, 0.0, 4.0]
+    y[2] = 1.0
+    om = np.ones(n)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, False, tmp)
+        f = np.zeros((4, n))
+        Dv = np.zeros(n)
+        lib.host_eval(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), _ptrs([]),
+                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+    assert Dv[0] == np.inf and Dv[1] == 0.0, Dv
+    assert abs(Dv[2] - np.exp(-0.5)) <= 2e-16 * np.exp(-0.5)
