@@ -195,6 +195,39 @@ def test_exp_within_ulps():
     assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
 
 
+def test_exp_of_nonpositive_argument_within_ulps():
+    """The device exponential without the overflow clamp, which the emitter
+    takes where the graph proves the argument non-positive (here -x0^2):
+    within 1.5 ulp of the correctly rounded e^(-x0^2), and exact at 0, -0,
+    at underflow, at +-inf and NaN (D = omega e^(-x0^2), omega = 1)."""
+    from paper_2508_15967_amd import raygraph as rgb
+    from tests.test_emit_host import _exp_reference, _exp_ulps
+    torch = U.torch_mod()
+    g = rgb.Graph(2)
+    prog = g.compile(g.omega * (-(g.x(0) * g.x(0))).exp())
+    assert "rg_exp_np(" in prog.functions()
+    rng = np.random.default_rng(29)
+    x = np.concatenate([rng.uniform(0.0, 28.0, 4000), rng.uniform(0.0, 1.0, 2000),
+                        rng.uniform(-5.0, 5.0, 2000)])
+    special = np.array([0.0, -0.0, 27.3, 33.4, 40.0, 1e200, np.inf, -np.inf, np.nan])
+    xs = np.concatenate([x, special])
+    y = np.zeros((4, xs.size))
+    y[0] = xs
+    y[2] = 1.0
+    _, D = prog.eval(U.dev(y), U.dev(np.ones(xs.size)))
+    torch.cuda.synchronize()
+    Dv = D.cpu().numpy()
+    with np.errstate(over="ignore", invalid="ignore"):
+        arg = -(xs * xs)
+    assert _exp_ulps(Dv[:x.size], _exp_reference(arg[:x.size])).max() <= 1.5
+    got_sp = Dv[x.size:]
+    with np.errstate(over="ignore", invalid="ignore"):
+        ref_sp = np.exp(arg[x.size:])
+    same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
+    same |= np.isfinite(ref_sp) & (ref_sp > 0) & (_exp_ulps(got_sp, ref_sp) <= 1.5)
+    assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+
+
 @pytest.mark.parametrize("cfg", ["1", "4", "5"])
 def test_newton_launch_conditions_match_oracle(oracle, cfg):
     """GPU Newton solve of D = 0 for k_x (rg_solve_k) against the oracle's
