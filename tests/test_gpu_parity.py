@@ -89,6 +89,38 @@ def test_stratified_full_size_sampled(oracle):
     torch.cuda.empty_cache()
 
 
+def test_trajectory_beyond_2_31_elements(oracle):
+    """Four copies of workload 2 (4,194,304 rays x 10,000 steps, 101
+    snapshots of 6 components: 2.5e9 trajectory elements, 20 GB) exercise
+    64-bit indexing of the trajectory store.  Sampled rays of the last copy,
+    whose later snapshots lie beyond element 2^31, match the oracle, and the
+    copies agree bitwise."""
+    torch = U.torch_mod()
+    w1 = W.make("2")
+    n1 = w1.n
+    w = w1.select(np.tile(np.arange(n1), 4))
+    _print_case("strat_x4_traj_64bit", w)
+    _, _, prog, params = U.program(w)
+    out = prog.trace(U.dev(w.x0), U.dev(w.k0), U.dev(w.omega), [U.dev(p) for p in params],
+                     store=True, integrator=w.integrator, dt=w.dt, n_steps=w.n_steps,
+                     store_every=w.store_every)
+    torch.cuda.synchronize()
+    traj = out["traj"]
+    # element offset of snapshot s, component c, ray r: (6 s + c) n + r
+    assert (traj.shape[0] - 1) * 6 * w.n > 2 ** 31
+    loc = np.sort(np.random.default_rng(7).choice(n1, 64, replace=False))
+    last = traj[:, :, torch.from_numpy(3 * n1 + loc).to(traj.device)].cpu().numpy()
+    first = traj[:, :, torch.from_numpy(loc).to(traj.device)].cpu().numpy()
+    assert np.array_equal(first, last)
+    ws = w1.select(loc)
+    o = oracle.trace(ws, store=True)
+    ex, ek = U.traj_errors(last, o["traj"], ws.omega, w.dim)
+    assert ex < U.TOL and ek < U.TOL, (ex, ek)
+    assert bool((out["status"] == 0).all()) and bool((out["steps"] == w.n_steps).all())
+    del out, traj
+    torch.cuda.empty_cache()
+
+
 def test_spline_forward(oracle):
     w = W.make("4", 2048)
     w.n_steps = 2000
