@@ -361,13 +361,15 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         I.vjp_flops_issued = fl_vjp.issued;
         I.vjp_flops_ray_invariant = fl_vjp.inv_alg;
         // reverse of one step: recompute (one RK4 step) [+ 3 stage RHS and
-        // 3 stage fma when the stages are recomputed; three of the four VJPs
-        // then run at states whose right-hand side the step evaluates, and
-        // what the two share counts once] + 4 VJP + recurrence (per
-        // component: 3 fma, 3 add, 1 mul, 1 add = 12 flops)
+        // 3 stage fma when the stages are recomputed] + 4 VJP + recurrence
+        // (per component: 3 fma, 3 add, 1 mul, 1 add = 12 flops).  Three of
+        // the four VJPs run at states whose right-hand side the step
+        // evaluates: the algorithmic count takes what the two share once,
+        // the issued count all of it, since the kernel recomputes the shared
+        // part inside the VJP rather than keep it live across the stages.
         const double rec = 12.0 * ny;
         const double st_alg = p->adj_recompute ? 3 * (fl_rhs_vjp.alg - fl_vjp.alg) + 6.0 * ny : 0.0;
-        const double st_iss = p->adj_recompute ? 3 * (fl_rhs_vjp.issued - fl_vjp.issued) + 6.0 * ny : 0.0;
+        const double st_iss = p->adj_recompute ? 3 * fl_rhs.issued + 6.0 * ny : 0.0;
         I.adj_step_flops_alg = I.rk4_step_flops_alg + st_alg + 4 * fl_vjp.alg + rec;
         I.adj_step_flops_issued = I.rk4_step_flops_issued + st_iss + 4 * fl_vjp.issued + rec;
     }
