@@ -615,13 +615,47 @@ static double dp_factor(double err, double facmax)
     return fac;
 }
 
+/* One Dormand-Prince attempt of size hs from (y, K1 = f(y)): the stage
+ * derivatives K[0..6] (K[6] = f(y5), first-same-as-last), the 5th-order
+ * solution y5 (propagated), the difference e = y5 - y4 to the embedded
+ * 4th-order solution, and the scaled RMS error
+ *   err = sqrt(mean_i (e_i / sc_i)^2),  sc_i = atol + rtol max(|y_i|, |y5_i|)
+ * over the 2d components of (x, k). */
+static double dopri_attempt(const om_medium *m, const double *y, double w, double hs,
+                            double rtol, double atol, double K[7][MAXY], double *y5, double *e)
+{
+    int n2 = 2 * m->dim;
+    double Y[MAXY];
+    for (int s = 1; s < 7; s++) {
+        for (int i = 0; i < n2; i++) {
+            double acc_i = 0.0;
+            for (int j = 0; j < s; j++) acc_i += DP_A[s][j] * K[j][i];
+            Y[i] = y[i] + hs * acc_i;
+        }
+        om_eval(m, Y, w, K[s], NULL);
+    }
+    /* the last stage is evaluated at the 5th-order solution (FSAL) */
+    for (int i = 0; i < n2; i++) y5[i] = Y[i];
+    double sum = 0.0;
+    for (int i = 0; i < n2; i++) {
+        double ei = 0.0;
+        for (int j = 0; j < 7; j++) ei += (DP_B5[j] - DP_B4[j]) * K[j][i];
+        ei = hs * ei;
+        e[i] = ei;
+        double ay = fabs(y[i]), ay5 = fabs(y5[i]);
+        double sc = atol + rtol * (ay > ay5 ? ay : ay5);
+        sum += (ei / sc) * (ei / sc);
+    }
+    return sqrt(sum / (double)n2);
+}
+
 static void trace_dopri_ray(const om_medium *m, const om_opts *o, int64_t n, int64_t r,
                             const double *x0, const double *k0, const double *omega,
                             double *x_out, double *k_out, double *t_out,
                             int32_t *status, int32_t *steps, int32_t *attempts_out)
 {
     int d = m->dim, n2 = 2 * d;
-    double y[MAXY], K[7][MAXY], Y[MAXY], y5[MAXY];
+    double y[MAXY], K[7][MAXY], y5[MAXY], e[MAXY];
     for (int i = 0; i < d; i++) { y[i] = x0[i * n + r]; y[d + i] = k0[i * n + r]; }
     double w = omega[r], t = 0.0, h = o->h0, facmax = 5.0;
     int64_t budget = o->budget ? o->budget[r] : o->max_steps;
@@ -633,26 +667,7 @@ static void trace_dopri_ray(const om_medium *m, const om_opts *o, int64_t n, int
         if (o->t_end > 0.0 && t >= o->t_end) { st = RAY_OK; break; }
         double hs = h;
         if (o->t_end > 0.0 && t + hs > o->t_end) hs = o->t_end - t;
-        for (int s = 1; s < 7; s++) {
-            for (int i = 0; i < n2; i++) {
-                double acc_i = 0.0;
-                for (int j = 0; j < s; j++) acc_i += DP_A[s][j] * K[j][i];
-                Y[i] = y[i] + hs * acc_i;
-            }
-            om_eval(m, Y, w, K[s], NULL);
-        }
-        /* the last stage is evaluated at the 5th-order solution (FSAL) */
-        for (int i = 0; i < n2; i++) y5[i] = Y[i];
-        double sum = 0.0;
-        for (int i = 0; i < n2; i++) {
-            double e = 0.0;
-            for (int j = 0; j < 7; j++) e += (DP_B5[j] - DP_B4[j]) * K[j][i];
-            e = hs * e;
-            double ay = fabs(y[i]), ay5 = fabs(y5[i]);
-            double sc = o->atol + o->rtol * (ay > ay5 ? ay : ay5);
-            sum += (e / sc) * (e / sc);
-        }
-        double err = sqrt(sum / (double)n2);
+        double err = dopri_attempt(m, y, w, hs, o->rtol, o->atol, K, y5, e);
         att++;
         if (err <= 1.0 && all_finite(y5, n2) && all_finite(K[6], n2)) {
             memcpy(y, y5, sizeof(double) * n2);
@@ -674,6 +689,22 @@ static void trace_dopri_ray(const om_medium *m, const om_opts *o, int64_t n, int
     status[r] = st;
     steps[r] = (int32_t)acc;
     if (attempts_out) attempts_out[r] = (int32_t)att;
+}
+
+/* One Dormand-Prince attempt of size h from each point (for tests of the
+ * error estimate): y SoA [2d][n]; y5 and e SoA [2d][n]; err [n]. */
+int om_dopri_attempt(const om_medium *m, int64_t n, const double *y, const double *omega, double h,
+                     double rtol, double atol, double *y5, double *e, double *err)
+{
+    int n2 = 2 * m->dim;
+    for (int64_t r = 0; r < n; r++) {
+        double yy[MAXY], K[7][MAXY], y5r[MAXY], er[MAXY];
+        for (int i = 0; i < n2; i++) yy[i] = y[i * n + r];
+        om_eval(m, yy, omega[r], K[0], NULL);
+        err[r] = dopri_attempt(m, yy, omega[r], h, rtol, atol, K, y5r, er);
+        for (int i = 0; i < n2; i++) { y5[i * n + r] = y5r[i]; e[i * n + r] = er[i]; }
+    }
+    return 0;
 }
 
 static void set_threads(int nt)
@@ -876,12 +907,19 @@ void om_dopri_tableau(double *c, double *a, double *b5, double *b4)
     }
 }
 
-/* dD/dk by hand: isotropic media and the O-mode profile 2k; anisotropic
- * medium 2 A k. */
-static void om_Dk(const om_medium *m, const double *y, double *Dk)
+/* dD/dk: by hand for the isotropic media and the O-mode profile (2k) and
+ * the anisotropic medium (2 A k); for the cold plasma the complex-step
+ * partials of its D (eqs. 5-10). */
+static void om_Dk(const om_medium *m, const double *y, double w, double *Dk)
 {
     int d = m->dim;
     const double *x = y, *k = y + d;
+    if (m->kind == COLDPLASMA) {
+        double D, g[6], Dw;
+        cp_grad(m, y, w, &D, g, &Dw);
+        for (int i = 0; i < 3; i++) Dk[i] = g[3 + i];
+        return;
+    }
     if (m->kind != ANISO3D) {
         for (int i = 0; i < d; i++) Dk[i] = 2.0 * k[i];
         return;
@@ -916,7 +954,7 @@ int om_newton_k(const om_medium *m, int64_t n, const double *x, double *k, const
         for (;;) {
             if (fabs(D) <= tol) { done = 1; break; }
             if (it >= max_iter || !isfinite(D)) break;
-            om_Dk(m, y, Dk);
+            om_Dk(m, y, omega[r], Dk);
             y[d + c] = y[d + c] - D / Dk[c];
             it++;
             D = om_D1(m, y, omega[r]);

@@ -221,6 +221,20 @@ def dp_factor(err: float, facmax: float = 5.0) -> float:
     return float(lib().om_dp_factor(float(err), float(facmax)))
 
 
+def dopri_attempt(medium, y, omega, h, rtol, atol):
+    """One Dormand-Prince attempt of size h from each point y (SoA [2d][n]):
+    returns (5th-order solution y5, error vector e = y5 - y4, scaled RMS
+    error err)."""
+    med = Medium(medium)
+    y = _f64(y)
+    n = y.shape[1]
+    om = _f64(np.broadcast_to(omega, (n,)))
+    y5, e, err = np.zeros_like(y), np.zeros_like(y), np.zeros(n)
+    lib().om_dopri_attempt(C.byref(med.s), C.c_int64(n), _ptr(y), _ptr(om), C.c_double(h),
+                           C.c_double(rtol), C.c_double(atol), _ptr(y5), _ptr(e), _ptr(err))
+    return y5, e, err
+
+
 def dopri_tableau():
     c, a, b5, b4 = np.zeros(7), np.zeros((7, 6)), np.zeros(7), np.zeros(7)
     lib().om_dopri_tableau(_ptr(c), _ptr(a), _ptr(b5), _ptr(b4))

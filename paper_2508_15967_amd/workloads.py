@@ -99,6 +99,10 @@ class Workload:
     targets: Optional[np.ndarray] = None  # (dim, n)
     ckpt_every: int = 0
     fd_params: Optional[np.ndarray] = None  # parameter indices checked by FD
+    # launch by Newton's method: k0[solve_k] is an initial guess (its sign and
+    # size select the branch) to be replaced by the root of D = 0 in that
+    # component before tracing; -1: k0 is already on the dispersion surface
+    solve_k: int = -1
 
     @property
     def n(self) -> int:
@@ -130,6 +134,10 @@ class Workload:
             w.targets = np.ascontiguousarray(self.targets[:, :n])
         return w
 
+
+# hydrogen ion to electron mass ratio; n_z of the oblique cold-plasma launches
+MU_H = 1836.15267343
+CP_NZ = 0.2
 
 FULL_RAYS = {"1": 1024, "1b": 1024, "2": 1048576, "3": 4194304, "4": 65536, "5": 1048576}
 
@@ -320,8 +328,11 @@ def make(cfg: str, n_rays: Optional[int] = None) -> Workload:
         return aniso3d(n_rays)
     if cfg == "cp":
         # the paper's own physics at its benchmark scale: 1,048,576 O-mode
-        # rays in the cold-plasma slab, to the plasma cut-off and back
-        return coldplasma("O", n_rays if n_rays is not None else 1048576, dt=1e-2, n_steps=4000)
+        # rays in a two-species (electron, hydrogen ion) cold-plasma slab,
+        # launched obliquely to B with k_x found by Newton's method, to the
+        # plasma cut-off and back
+        return coldplasma("O", n_rays if n_rays is not None else 1048576, dt=1e-2, n_steps=4000,
+                          mu=MU_H, nz=CP_NZ)
     raise ValueError(f"unknown workload {cfg!r}")
 
 
@@ -390,19 +401,32 @@ def _stix(med, x, w):
 
 
 def coldplasma(mode: str = "O", n_rays: int = 64, seed: int = 14, x0: float = -5.0,
-               direction: float = 1.0, dt: float = 1e-2, n_steps: int = 2000) -> Workload:
-    """Rays in the xy-plane (k_z = 0, perpendicular to B) launched on the O- or
-    X-mode branch.  Profile: X = w_pe^2/w^2 = 0.5 (0.1 x + 1), |Omega_e| = 0.5 w,
-    so the O cut-off (X = 1) is at x = 10, the upper-hybrid resonance
+               direction: float = 1.0, dt: float = 1e-2, n_steps: int = 2000, mu: float = 0.0,
+               nz: float = 0.0) -> Workload:
+    """Rays launched in the cold-plasma slab on the O- or X-mode branch.
+    Profile: X = w_pe^2/w^2 = 0.5 (0.1 x + 1), Omega_e = -0.5 w, so for
+    electrons the O cut-off (X = 1) is at x = 10, the upper-hybrid resonance
     (X = 0.75) at x = 5, the R cut-off (X = 0.5) at x = 0 and the L cut-off
-    (X = 1.5) at x = 20."""
+    (X = 1.5) at x = 20.
+
+    With mu = 0 and nz = 0 (electrons only, k perpendicular to B) the launch
+    wavevector is on the branch's closed-form shell n^2 = P (O) or R L / S
+    (X).  With an ion species (mass ratio mu > 0) or an oblique n_z = nz,
+    k_z = nz w is fixed and k_x holds an initial guess for Newton's method
+    (``solve_k = 0``): the electron-only perpendicular root of the branch,
+    whose sign (direction) and size select the root of the full D."""
     rng = np.random.default_rng(seed)
-    med = Medium(COLDPLASMA, 3, p=np.array([0.5, 0.1, -0.5, 0.0, 0, 0, 0, 0.0]))
+    med = Medium(COLDPLASMA, 3, p=np.array([0.5, 0.1, -0.5, float(mu), 0, 0, 0, 0.0]))
     x = np.stack([np.full(n_rays, x0), rng.uniform(-1, 1, n_rays), np.zeros(n_rays)])
     w = np.ones(n_rays)
-    S, Dst, P = _stix(med, x[0], w)
+    el = Medium(COLDPLASMA, 3, p=np.array([0.5, 0.1, -0.5, 0.0, 0, 0, 0, 0.0]))
+    S, Dst, P = _stix(el, x[0], w)
     n2 = P if mode == "O" else (S * S - Dst * Dst) / S   # perpendicular: P or RL/S
     ky = rng.uniform(-0.1, 0.1, n_rays) * np.sqrt(np.abs(n2))
-    kx = direction * np.sqrt(n2 * w ** 2 - ky ** 2)
-    k = np.stack([kx, ky, np.zeros(n_rays)])
-    return Workload(f"coldplasma_{mode}", "c" + mode, 3, med, x, k, w, RK4, dt=dt, n_steps=n_steps)
+    kz = np.full(n_rays, nz) * w
+    kx = direction * np.sqrt(n2 * w ** 2 - ky ** 2 - kz ** 2)
+    k = np.stack([kx, ky, kz])
+    oblique = mu > 0 or nz != 0
+    name = f"coldplasma_{mode}" + ("2" if oblique else "")
+    return Workload(name, "c" + mode + ("2" if oblique else ""), 3, med, x, k, w, RK4, dt=dt,
+                    n_steps=n_steps, solve_k=0 if oblique else -1)

@@ -74,10 +74,45 @@ def _coldplasma_D(med, x, k, w):
     return det
 
 
-def D_of(med, x, k, w):
-    """D for every medium kind; arrays (dim, n), w shape (n,)."""
+def stix_RLP(med, x, w):
+    """Stix R, L, P from the per-species sums (B along z, density profile
+    w_pe^2 = p0 (p1 x + 1) of eq. 4, signed cyclotron frequency p2 of the
+    electrons; with p3 > 0 one ion species of mass ratio p3, singly charged,
+    quasi-neutral): R = 1 - sum_s X_s/(1 + Y_s), L = 1 - sum_s X_s/(1 - Y_s),
+    P = 1 - sum_s X_s with X_s = w_ps^2/w^2, Y_s = Omega_s/w."""
+    Xe = med.p[0] * (med.p[1] * x[0] + 1.0) / (w * w)
+    Ye = med.p[2] / w
+    species = [(Xe, Ye)]
+    if med.p[3] > 0:
+        species.append((Xe / med.p[3], -Ye / med.p[3]))
+    R = 1.0 - sum(Xs / (1.0 + Ys) for Xs, Ys in species)
+    L = 1.0 - sum(Xs / (1.0 - Ys) for Xs, Ys in species)
+    P = 1.0 - sum(Xs for Xs, _ in species)
+    return R, L, P
+
+
+def _coldplasma_D_stix(med, x, k, w):
+    """The same determinant in the Stix form A n^4 - B n^2 + C with
+    A = S sin^2 + P cos^2, B = R L sin^2 + P S (1 + cos^2), C = P R L
+    (angle between n and B along z; S = (R + L)/2), written with
+    n^2 sin^2 = n_x^2 + n_y^2 and n^2 cos^2 = n_z^2 so that it is a
+    polynomial in the components of n: real arithmetic throughout, hence
+    analytic and fit for complex-step differentiation."""
+    R, L, P = stix_RLP(med, x, w)
+    S = 0.5 * (R + L)
+    n = [k[i] / w for i in range(3)]
+    q = n[0] * n[0] + n[1] * n[1]   # n^2 sin^2
+    z = n[2] * n[2]                 # n^2 cos^2
+    n2 = q + z
+    return (S * q + P * z) * n2 - (R * L * q + P * S * (n2 + z)) + P * R * L
+
+
+def D_of(med, x, k, w, stix=False):
+    """D for every medium kind; arrays (dim, n), w shape (n,).  For the cold
+    plasma: the explicit complex determinant, or with stix=True its real
+    Stix-polynomial form."""
     if med.kind == W.COLDPLASMA:
-        return _coldplasma_D(med, x, k, w)
+        return _coldplasma_D_stix(med, x, k, w) if stix else _coldplasma_D(med, x, k, w)
     if med.kind == W.ANISO3D:
         D = (k * k).sum(0) - w * w
         for b in range(len(med.scales)):
@@ -114,9 +149,8 @@ def rhs_central_diff(med, y, w, h=1e-6):
 
 
 def rhs_complex_step(med, y, w, h=1e-30):
-    """Ray right-hand side from complex-step partials of D."""
-    if med.kind == W.COLDPLASMA:
-        return rhs_central_diff(med, y, w)
+    """Ray right-hand side from complex-step partials of D (for the cold
+    plasma, of its real Stix-polynomial form)."""
     d = y.shape[0] // 2
     n = y.shape[1]
     yc = y.astype(np.complex128)
@@ -125,8 +159,8 @@ def rhs_complex_step(med, y, w, h=1e-30):
     for i in range(2 * d):
         e = yc.copy()
         e[i] += 1j * h
-        grads[i] = np.imag(D_of(med, e[:d], e[d:], wc)) / h
-    Dw = np.imag(D_of(med, yc[:d], yc[d:], wc + 1j * h)) / h
+        grads[i] = np.imag(D_of(med, e[:d], e[d:], wc, stix=True)) / h
+    Dw = np.imag(D_of(med, yc[:d], yc[d:], wc + 1j * h, stix=True)) / h
     f = np.empty((2 * d, n))
     f[:d] = -grads[d:] / Dw
     f[d:] = grads[:d] / Dw

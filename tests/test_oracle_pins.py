@@ -105,22 +105,160 @@ def test_linearn_closed_form(oracle):
 MEDIA = ["1", "2", "3", "4", "5"]
 
 
-@pytest.mark.parametrize("cfg", MEDIA + ["homog", "olinear", "linearn", "coldO", "coldX"])
+COLD = {"coldO": lambda: W.coldplasma("O"), "coldX": lambda: W.coldplasma("X", x0=12.0),
+        # an ion species (eqs. 8-10 summed over species) and oblique launch
+        # (the n_parallel of eq. 6): a light ion (mass ratio 4) so that the
+        # ion terms are large, and hydrogen
+        "coldI": lambda: W.coldplasma("O", mu=4.0, nz=0.2),
+        "coldH": lambda: W.coldplasma("X", x0=12.0, mu=W.MU_H, nz=0.3)}
+
+
+@pytest.mark.parametrize("cfg", MEDIA + ["homog", "olinear", "linearn"] + list(COLD))
 def test_rhs_matches_complex_step_of_D(oracle, cfg):
-    w = {"homog": W.homog, "olinear": W.olinear, "linearn": W.linearn,
-         "coldO": lambda: W.coldplasma("O"), "coldX": lambda: W.coldplasma("X", x0=12.0)}.get(
+    w = {"homog": W.homog, "olinear": W.olinear, "linearn": W.linearn, **COLD}.get(
         cfg, lambda: W.make(cfg, 4096))()
     rng = np.random.default_rng(100)
     y, om = _random_states(w, 500, rng)
     if cfg.startswith("cold"):
         y[5] = 0.3 * rng.uniform(-1, 1, y.shape[1])  # oblique k_z as well
     f, D, _ = oracle.eval_points(w.medium, y, om)
+    # for the cold plasma: complex step of the Stix-polynomial form of the
+    # determinant (tests/dispersion_defs.py), against the oracle's complex
+    # step of the determinant as the paper writes it (eqs. 5-10): two
+    # exact derivative routes, which still differ by the rounding of the
+    # partials, differences of O(1) products that cancel near the
+    # dispersion surface (measured up to 8e-13 of f; 1e-15 in the X-mode
+    # sets)
     fr = DD.rhs_complex_step(w.medium, y, om)
     scale = np.abs(fr).max(axis=0) + 1e-300
-    tol = 1e-7 if cfg.startswith("cold") else 1e-13   # central differences there
+    tol = 1e-12 if cfg.startswith("cold") else 1e-13
     assert (np.abs(f - fr).max(axis=0) / scale).max() < tol
     Dr = np.real(DD.D_of(w.medium, y[: w.dim], y[w.dim:], om))
     assert np.abs(D - Dr).max() < 1e-13 * (1 + np.abs(Dr).max())
+
+
+@pytest.mark.parametrize("mu", [0.0, 4.0, W.MU_H])
+def test_coldplasma_D_is_stix_polynomial(oracle, mu):
+    """Cold plasma (eqs. 5-10) with B along z: the determinant equals
+    A n^4 - B n^2 + C with A = S sin^2 + P cos^2, B = R L sin^2 + P S
+    (1 + cos^2), C = P R L, where R, L, P are the per-species sums
+    1 - sum X_s/(1 +- Y_s), 1 - sum X_s (eqs. 8-10 with S = (R + L)/2 and
+    the off-diagonal element D_Stix = (R - L)/2).  Random oblique states
+    (every n component non-zero), electrons alone or with one ion species:
+    a slip in the ion branch (its X_i = X/mu, Y_i = -Y/mu) or in an
+    off-diagonal term fails this."""
+    rng = np.random.default_rng(200)
+    med = W.Medium(W.COLDPLASMA, 3, p=np.array([0.5, 0.1, -0.5, mu, 0, 0, 0, 0.0]))
+    n = 2000
+    x = np.stack([rng.uniform(-5, 25, n), rng.uniform(-2, 2, n), rng.uniform(-2, 2, n)])
+    k = rng.uniform(-1.5, 1.5, (3, n))
+    om = rng.uniform(0.8, 1.3, n)
+    _, D, _ = oracle.eval_points(med, np.concatenate([x, k]), om)
+    Ds = np.real(DD.D_of(med, x, k, om, stix=True))
+    R, L, P = DD.stix_RLP(med, x, om)
+    S = 0.5 * (R + L)
+    nn = k / om
+    q, z = nn[0] ** 2 + nn[1] ** 2, nn[2] ** 2
+    terms = (np.abs(S * q * (q + z)) + np.abs(P * z * (q + z)) + np.abs(R * L * q)
+             + np.abs(P * S * (q + 2 * z)) + np.abs(P * R * L))
+    assert (np.abs(D - Ds) / terms).max() < 1e-14
+    if mu > 0:
+        # and the ion species matters at these points
+        med0 = W.Medium(W.COLDPLASMA, 3, p=np.array([0.5, 0.1, -0.5, 0.0, 0, 0, 0, 0.0]))
+        _, D0, _ = oracle.eval_points(med0, np.concatenate([x, k]), om)
+        assert np.median(np.abs(D - D0) / terms) > (1e-2 if mu < 10 else 1e-6)
+
+
+def _stix_q_roots(med, x, k, om):
+    """Roots q = n_x^2 + n_y^2 of the Stix form at fixed n_z (a quadratic in
+    q: S q^2 + ((S + P) z - R L - P S) q + P (z^2 - 2 S z + R L), z = n_z^2);
+    for z = 0 they are P (O-mode) and R L / S (X-mode)."""
+    R, L, P = DD.stix_RLP(med, x, om)
+    S = 0.5 * (R + L)
+    z = (k[2] / om) ** 2
+    a, b, c = S, (S + P) * z - R * L - P * S, P * (z * z - 2 * S * z + R * L)
+    disc = np.sqrt(b * b - 4 * a * c)
+    return (-b + disc) / (2 * a), (-b - disc) / (2 * a)
+
+
+@pytest.mark.parametrize("case", ["O", "X", "O2", "X2"])
+def test_newton_coldplasma_closed_form(oracle, case):
+    """Newton on k_x for the cold-plasma D (end of the "Impact" section:
+    launch conditions from Newton's method, the initial guess selecting the
+    branch), perpendicular electrons-only (roots n^2 = P for O and R L / S
+    for X) and oblique with hydrogen ions (the roots of the Stix quadratic
+    in n_perp^2): the oracle converges to |D| <= 1e-15 and to the root of
+    the branch its guess lies on, with the guess's sign."""
+    mode = case[0]
+    x0 = -5.0 if mode == "O" else 12.0
+    extra = dict(mu=W.MU_H, nz=0.2) if case.endswith("2") else {}
+    w = W.coldplasma(mode, n_rays=128, x0=x0, **extra)
+    rng = np.random.default_rng(22)
+    guess = w.k0.copy()
+    sign = np.where(rng.random(w.n) < 0.5, -1.0, 1.0)
+    # the O and X roots lie within 10 % of each other here and D has a
+    # shallow extremum between them: guesses within 1 % of a root stay in
+    # its basin
+    guess[0] = sign * np.abs(guess[0]) * (1 + 0.01 * rng.uniform(-1, 1, w.n))
+    k, it, D = oracle.newton_k(w.medium, w.x0, guess, w.omega, 0, 1e-15, 50)
+    assert np.all(it >= 0) and np.abs(D).max() <= 1e-15
+    qa, qb = _stix_q_roots(w.medium, w.x0, k, w.omega)
+    if not case.endswith("2"):
+        R, L, P = DD.stix_RLP(w.medium, w.x0, w.omega)
+        want_q = P if mode == "O" else R * L / (0.5 * (R + L))
+    else:
+        # the root nearest the guess's n_perp^2 is the branch it selects
+        qg = (guess[0] ** 2 + guess[1] ** 2) / w.omega ** 2
+        want_q = np.where(np.abs(qa - qg) < np.abs(qb - qg), qa, qb)
+    exact = sign * w.omega * np.sqrt(want_q - (guess[1] / w.omega) ** 2)
+    assert np.all(np.sign(k[0]) == sign)
+    assert np.abs(k[0] - exact).max() <= 1e-13 * np.abs(exact).max()
+    assert np.array_equal(k[1:], guess[1:])
+
+
+@pytest.mark.parametrize("case", ["X", "X2", "O2"])
+def test_coldplasma_turning_points_from_stix_quadratic(oracle, case):
+    """Rays of the full cold-plasma D (eqs. 5-10) turn where n_x = 0, i.e.
+    where the Stix quadratic has the root n_perp^2 = n_y^2 (n_y and n_z are
+    conserved: D depends on x alone).  The turning points are found by
+    bisection of that quadratic, written from the per-species R, L, P; the
+    oracle's largest x on a fine trajectory must match them.  X-mode from
+    x = 12 toward the L cut-off, electrons only and with hydrogen ions at
+    oblique n_z = 0.2; oblique O-mode with ions from x = -5 toward the plasma
+    cut-off."""
+    mode = case[0]
+    x0 = 12.0 if mode == "X" else -5.0
+    extra = dict(mu=W.MU_H, nz=0.2) if case.endswith("2") else {}
+    w = W.coldplasma(mode, n_rays=16, x0=x0, direction=1.0, dt=1e-2,
+                     n_steps=6000, **extra)
+    if w.solve_k >= 0:
+        w.k0, it, _ = oracle.newton_k(w.medium, w.x0, w.k0, w.omega, 0, 1e-15, 50)
+        assert np.all(it >= 0)
+    w.store_every = 1
+    r = oracle.trace(w, store=True)
+    assert np.all(r["status"] == oracle.RAY_OK)
+    xmax = r["traj"][:, 0].max(axis=0)
+    for i in range(w.n):
+        ny2 = (w.k0[1, i] / w.omega[i]) ** 2
+        n0 = np.array([[1.0], [w.k0[1, i]], [w.k0[2, i]]])
+
+        def g(x):
+            # which root of the quadratic the ray is on at its launch point
+            # decides the sign convention: F(x) = Q(x) - n_y^2 for that root
+            qa, qb = _stix_q_roots(w.medium, np.array([[x], [0.0], [0.0]]), n0, w.omega[i:i + 1])
+            return (qa if branch == 0 else qb)[0] - ny2
+
+        q0 = (w.k0[0, i] ** 2 + w.k0[1, i] ** 2) / w.omega[i] ** 2
+        qa, qb = _stix_q_roots(w.medium, w.x0[:, i:i + 1], n0, w.omega[i:i + 1])
+        branch = 0 if abs(qa[0] - q0) < abs(qb[0] - q0) else 1
+        lo, hi = x0, x0 + 0.5
+        while g(hi) > 0:
+            hi += 0.5
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if g(mid) > 0 else (lo, mid)
+        assert abs(xmax[i] - lo) < 1e-4, (i, xmax[i], lo)
+    assert np.all(r["k"][0] < 0)   # turned around
 
 
 @pytest.mark.parametrize("cfg", MEDIA + ["olinear", "linearn"])
@@ -535,3 +673,57 @@ def test_dopri_step_factor_definition(oracle):
         # a few ulp away from the rounding point the decision is exact
         for e in (t * (1 - 8 * 2.0 ** -52), t * (1 + 8 * 2.0 ** -52)):
             assert oracle.dp_factor(e, 5.0) == exact(e, 5.0), (k, e)
+
+
+def test_snapshot_times_homogeneous(oracle):
+    """Snapshot j of a trace stored every se steps is the state after j*se
+    steps: in a homogeneous medium x_j = x0 + k0 j se dt/(w N0) and k_j = k0.
+    A step count that is not a multiple of se leaves a final partial
+    interval without a snapshot (n_steps // se + 1 snapshots)."""
+    w = W.homog(n_rays=32)
+    w.n_steps, w.store_every = 103, 10
+    r = oracle.trace(w, store=True)
+    N0 = w.medium.p[0]
+    traj = r["traj"]
+    assert traj.shape[0] == 103 // 10 + 1
+    for j in range(traj.shape[0]):
+        xe = w.x0 + w.k0 * (j * 10 * w.dt) / (w.omega * N0)
+        assert np.abs(traj[j, :3] - xe).max() <= 1e-13 * (1 + np.abs(xe).max()), j
+        assert np.array_equal(traj[j, 3:], w.k0)
+
+
+def test_dopri_error_estimate_orders(oracle):
+    """One Dormand-Prince attempt from points of the linear-N medium, whose
+    rays have a closed form: the propagated 5th-order solution has a local
+    error O(h^6), the embedded 4th-order one (y5 - e) O(h^5), and the error
+    estimate e itself scales as h^5 (ratio 32 per halving of h).  With
+    rtol = 0 and atol = 1 the scaled error is the RMS of e."""
+    w = W.linearn(n_rays=8)
+    y = np.concatenate([w.x0, w.k0])
+    res = {}
+    for h in (0.4, 0.2, 0.1, 0.05):
+        y5, e, err = oracle.dopri_attempt(w.medium, y, w.omega, h, 0.0, 1.0)
+        xe, ke = _linearn_exact(w, h)
+        ex = np.concatenate([xe, ke])
+        res[h] = (np.abs(y5 - ex).max(), np.abs(y5 - e - ex).max(), np.abs(e).max())
+        assert np.allclose(err, np.linalg.norm(e, axis=0) / np.sqrt(6), rtol=1e-15, atol=0)
+    o5 = [np.log2(res[a][0] / res[b][0]) for a, b in ((0.4, 0.2), (0.2, 0.1))]
+    o4 = [np.log2(res[a][1] / res[b][1]) for a, b in ((0.2, 0.1), (0.1, 0.05))]
+    oe = [np.log2(res[a][2] / res[b][2]) for a, b in ((0.2, 0.1), (0.1, 0.05))]
+    assert all(abs(o - 6.0) < 0.25 for o in o5), o5
+    assert all(abs(o - 5.0) < 0.25 for o in o4), o4
+    assert all(abs(o - 5.0) < 0.25 for o in oe), oe
+
+
+def test_dopri_step_underflow(oracle):
+    """An attempt that fails so badly that its shrink factor takes the step
+    below hmin ends the ray with STEP_UNDERFLOW at its last accepted state:
+    h0 = 2 at rtol = atol = 1e-12 on the lens is rejected with the minimum
+    factor 0.2, and hmin = 0.5 then stops the ray after one attempt."""
+    w = W.make("1", 16)
+    w.integrator = W.DOPRI54
+    w.h0, w.rtol, w.atol, w.hmin = 2.0, 1e-12, 1e-12, 0.5
+    r = oracle.trace(w, max_steps=100)
+    assert np.all(r["status"] == oracle.RAY_STEP_UNDERFLOW)
+    assert np.all(r["steps"] == 0) and np.all(r["attempts"] == 1)
+    assert np.array_equal(r["x"], w.x0) and np.array_equal(r["k"], w.k0)
