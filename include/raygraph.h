@@ -248,6 +248,13 @@ typedef struct {
                                    checkpoints, program compiled with fp32 = 1); the
                                    arrays stay double, t and the traj_D residual
                                    are computed in double */
+    /* per-call device scratch, owned by the caller (a torch tensor): at least
+       the bytes rg_workspace_size reports for this description, 8-byte
+       aligned, overlapping no other buffer of the call.  NULL is allowed
+       when that size is 0 (persistent RK4 needs none).  Its contents on
+       entry do not matter; the call's stream work owns it until it ends. */
+    void *workspace;
+    size_t workspace_bytes;
 } rg_trace_desc;
 
 /* Trace n_rays rays.  RK4 runs exactly n_steps steps per ray (fewer if it
@@ -255,20 +262,44 @@ typedef struct {
  * or t_end is reached.  Requires a program compiled without compile_only.
  * n_rays = 0 returns RG_OK without touching any ray buffer (they may then
  * be NULL).  No output buffer may overlap an input buffer or another output
- * (RG_EINVAL): the autotuner's sample runs write the outputs first. */
+ * (RG_EINVAL): the autotuner's sample runs write the outputs first.
+ * The library allocates no device memory here: per-call scratch (the
+ * Dormand-Prince refill queue, the per-ray state of the one-launch-per-step
+ * forms) comes from d->workspace, so calls on different streams with
+ * different workspaces do not share state.  A workspace smaller than
+ * rg_workspace_size reports is RG_EINVAL. */
 rg_status rg_trace_rays(rg_program *p, const rg_trace_desc *d, void *hip_stream);
+
+/* Device workspace, in bytes, that rg_trace_rays needs for description d
+ * (its workspace fields are ignored).  Depends on the integrator, the mode
+ * and n_rays; 0 for persistent RK4.  Loads the program's code object on the
+ * current device if it is not loaded yet (so it needs a GPU). */
+rg_status rg_workspace_size(rg_program *p, const rg_trace_desc *d, size_t *bytes);
 
 typedef struct {
     uint32_t struct_size;       /* sizeof(rg_adjoint_desc) */
-    const rg_trace_desc *fwd;   /* the forward description (RK4 only); its
-                                   checkpoints and steps_out must hold the
-                                   results of rg_trace_rays on the same inputs */
+    const rg_trace_desc *fwd;   /* the forward description (RK4 only; its own
+                                   workspace fields are not used here).  Its
+                                   checkpoints and steps_out hold the results of
+                                   rg_trace_rays on the same inputs, or
+                                   checkpoints is NULL: the forward is then run
+                                   again inside this call (same launch form,
+                                   checkpoints every fwd->checkpoint_every steps
+                                   into the workspace; the caller's outputs are
+                                   not written) */
     const double *dL_dx_end;    /* [dim][n] */
     const double *dL_dk_end;    /* [dim][n], nullable = 0 */
     double *dL_dx0;             /* [dim][n], nullable */
     double *dL_dk0;             /* [dim][n], nullable */
     double *const *dL_dparams;  /* host array of n_params device pointers (entries
                                    nullable); overwritten, not accumulated */
+    /* per-call device scratch owned by the caller: at least the bytes
+       rg_adjoint_workspace_size reports (the segment buffer of stage states
+       and the per-workgroup gradient partials; with fwd->checkpoints NULL
+       also the internal forward's checkpoints and step counts), 8-byte
+       aligned, overlapping no other buffer of the call */
+    void *workspace;
+    size_t workspace_bytes;
 } rg_adjoint_desc;
 
 /* Discrete adjoint of the RK4 trajectory (exact transpose of the step map),
@@ -281,6 +312,14 @@ typedef struct {
  * between launches); results as the persistent form (per-ray gradients
  * bitwise, parameter gradients up to the summation order). */
 rg_status rg_trace_rays_adjoint(rg_program *p, const rg_adjoint_desc *d, void *hip_stream);
+
+/* Device workspace, in bytes, that rg_trace_rays_adjoint needs for d (its
+ * workspace fields are ignored).  The segment buffer holds, per resident
+ * lane of the adjoint launch (not per ray), the states of one checkpoint
+ * interval: checkpoint_every x (4 x 2 dim + 1) doubles where the stage
+ * states are stored, checkpoint_every x (2 dim + 1) where they are
+ * recomputed.  Loads the code object like rg_workspace_size. */
+rg_status rg_adjoint_workspace_size(rg_program *p, const rg_adjoint_desc *d, size_t *bytes);
 
 /* Elementwise evaluation of D and the right-hand side at n points (one
  * independent work item per point: inputs -> outputs, no time stepping).

@@ -17,6 +17,7 @@
 #ifndef RAYGRAPH_HAND_H
 #define RAYGRAPH_HAND_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -42,16 +43,21 @@ int32_t rg_hand_aniso_trace(const rg_hand_aniso *m, uint32_t n, const double *x0
                             int32_t n_steps, double *x_out, double *k_out, int32_t ckpt_every,
                             double *ckpt, int32_t block, void *hip_stream);
 
+/* Bytes of device workspace rg_hand_aniso_adjoint needs (per-lane segment
+ * states of ckpt_every steps and per-workgroup partial sums). */
+int32_t rg_hand_aniso_adjoint_workspace_size(uint32_t n, int32_t ckpt_every, int32_t block,
+                                             size_t *bytes);
+
 /* Discrete adjoint of the forward above: seeds dL/dx_end, dL/dk_end
  * (nullable) [3][n]; outputs dL/dx0, dL/dk0 [3][n] (nullable) and dL/ds [nb]
- * (nullable, overwritten).  Needs the checkpoints of the forward call.  The
- * library allocates its scratch (per-lane segment states and per-workgroup
- * partial sums) and keeps it for the next call. */
+ * (nullable, overwritten).  Needs the checkpoints of the forward call and a
+ * caller-owned device workspace of at least the size query's bytes. */
 int32_t rg_hand_aniso_adjoint(const rg_hand_aniso *m, uint32_t n, const double *omega,
                               const double *s, double dt, int32_t n_steps, int32_t ckpt_every,
                               const double *ckpt, const double *dL_dx_end,
                               const double *dL_dk_end, double *dL_dx0, double *dL_dk0,
-                              double *dL_ds, int32_t block, void *hip_stream);
+                              double *dL_ds, int32_t block, void *workspace,
+                              size_t workspace_bytes, void *hip_stream);
 
 const char *rg_hand_last_error(void);
 

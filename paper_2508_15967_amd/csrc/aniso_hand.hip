@@ -228,23 +228,6 @@ __global__ void hand_finalize(const double *gpart, int n_part, int nb, int strid
     out[b] = v;
 }
 
-struct Scratch {
-    void *p = nullptr;
-    size_t bytes = 0;
-} g_scratch;
-
-int32_t ensure_scratch(size_t bytes) {
-    if (bytes <= g_scratch.bytes) return 0;
-    if (g_scratch.p) (void)hipFree(g_scratch.p);
-    g_scratch.p = nullptr;
-    g_scratch.bytes = 0;
-    if (hipMalloc(&g_scratch.p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(-2, "scratch allocation failed");
-    }
-    g_scratch.bytes = bytes;
-    return 0;
-}
 
 template <class K>
 int32_t grid_for(K kern, int block, long long n, unsigned *grid) {
@@ -285,12 +268,10 @@ int32_t rg_hand_aniso_trace(const rg_hand_aniso *m, uint32_t n, const double *x0
     return e == hipSuccess ? 0 : fail(-4, hipGetErrorString(e));
 }
 
-int32_t rg_hand_aniso_adjoint(const rg_hand_aniso *m, uint32_t n, const double *omega, const double *s,
-                              double dt, int32_t n_steps, int32_t ckpt_every, const double *ckpt,
-                              const double *dL_dx_end, const double *dL_dk_end, double *dL_dx0,
-                              double *dL_dk0, double *dL_ds, int32_t block, void *stream) {
-    if (!m || !omega || !s || !ckpt || !dL_dx_end) return fail(-1, "NULL argument");
-    if (m->nb < 0 || m->nb > 16) return fail(-5, "at most 16 blobs in this build");
+int32_t rg_hand_aniso_adjoint_workspace_size(uint32_t n, int32_t ckpt_every, int32_t block,
+                                             size_t *bytes) {
+    if (!bytes) return fail(-1, "NULL argument");
+    *bytes = 0;
     if (ckpt_every <= 0) return fail(-1, "ckpt_every must be > 0");
     if (n == 0) return 0;
     if (block == 0) block = 256;
@@ -299,13 +280,33 @@ int32_t rg_hand_aniso_adjoint(const rg_hand_aniso *m, uint32_t n, const double *
     if (grid_for(hand_adjoint<16>, block, n, &grid)) return -4;
     const long long lanes = (long long)grid * block;
     const size_t scratch = (size_t)ckpt_every * 6 * lanes, part = (size_t)grid * 16;
-    if (ensure_scratch(8 * (scratch + part) + 512)) return -2;
+    *bytes = ((8 * scratch + 255) & ~(size_t)255) + 8 * part;
+    return 0;
+}
+
+int32_t rg_hand_aniso_adjoint(const rg_hand_aniso *m, uint32_t n, const double *omega, const double *s,
+                              double dt, int32_t n_steps, int32_t ckpt_every, const double *ckpt,
+                              const double *dL_dx_end, const double *dL_dk_end, double *dL_dx0,
+                              double *dL_dk0, double *dL_ds, int32_t block, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+    if (!m || !omega || !s || !ckpt || !dL_dx_end) return fail(-1, "NULL argument");
+    if (m->nb < 0 || m->nb > 16) return fail(-5, "at most 16 blobs in this build");
+    if (ckpt_every <= 0) return fail(-1, "ckpt_every must be > 0");
+    if (n == 0) return 0;
+    size_t need = 0;
+    if (int32_t st = rg_hand_aniso_adjoint_workspace_size(n, ckpt_every, block, &need)) return st;
+    if (!workspace || workspace_bytes < need) return fail(-1, "workspace smaller than the size query reports");
+    if (block == 0) block = 256;
+    unsigned grid;
+    if (grid_for(hand_adjoint<16>, block, n, &grid)) return -4;
+    const long long lanes = (long long)grid * block;
+    const size_t scratch = (size_t)ckpt_every * 6 * lanes;
     Args a{};
     a.omega = omega; a.s = s; a.ckpt = const_cast<double *>(ckpt); a.lam_x = dL_dx_end;
     a.lam_k = dL_dk_end; a.gx0 = dL_dx0; a.gk0 = dL_dk0; a.dt = dt; a.n = n; a.lanes = lanes;
     a.n_steps = n_steps; a.ckpt_every = ckpt_every;
-    a.scratch = (double *)g_scratch.p;
-    a.gpart = (double *)((char *)g_scratch.p + ((8 * scratch + 255) & ~(size_t)255));
+    a.scratch = (double *)workspace;
+    a.gpart = (double *)((char *)workspace + ((8 * scratch + 255) & ~(size_t)255));
     hipLaunchKernelGGL(hand_adjoint<16>, dim3(grid), dim3(block), 0, (hipStream_t)stream, *m, a);
     if (dL_ds)
         hipLaunchKernelGGL(hand_finalize, dim3(1), dim3(64), 0, (hipStream_t)stream,

@@ -271,6 +271,20 @@ rg_status rg_trace_rays_adjoint(rg_program *p, const rg_adjoint_desc *d, void *s
     GUARD_END
 }
 
+rg_status rg_workspace_size(rg_program *p, const rg_trace_desc *d, size_t *bytes) {
+    if (!p || !d || !bytes) return fail(RG_EINVAL, "NULL argument");
+    GUARD_BEGIN
+    return rg::workspace_size(p, *d, bytes);
+    GUARD_END
+}
+
+rg_status rg_adjoint_workspace_size(rg_program *p, const rg_adjoint_desc *d, size_t *bytes) {
+    if (!p || !d || !bytes) return fail(RG_EINVAL, "NULL argument");
+    GUARD_BEGIN
+    return rg::adjoint_workspace_size(p, *d, bytes);
+    GUARD_END
+}
+
 rg_status rg_solve_k(rg_program *p, const rg_solve_desc *d, void *stream) {
     if (!p || !d) return fail(RG_EINVAL, "NULL argument");
     GUARD_BEGIN

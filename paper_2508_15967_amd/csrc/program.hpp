@@ -1,5 +1,6 @@
 // Compiled program: generated source, gfx950 code object, kernel handles,
-// workspace, autotuning results and captured hipGraphs.
+// autotuning results and captured hipGraphs (no device buffers: per-call
+// scratch is the caller's workspace).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,8 +53,6 @@ struct rg_program {
     int n_cu = 0;
     hipModule_t module = nullptr;
     std::map<std::string, hipFunction_t> kernels;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
     std::map<std::string, TuneEntry> tune;
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
@@ -70,6 +69,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
 // Runtime (runtime.cpp).
 rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s);
 rg_status adjoint(rg_program *p, const rg_adjoint_desc &d, hipStream_t s);
+rg_status workspace_size(rg_program *p, const rg_trace_desc &d, size_t *bytes);
+rg_status adjoint_workspace_size(rg_program *p, const rg_adjoint_desc &d, size_t *bytes);
 rg_status solve_k(rg_program *p, const rg_solve_desc &d, hipStream_t s);
 rg_status eval_points(rg_program *p, uint32_t n, const double *y, const double *omega,
                       const double *t, const double *const *params, double *f, double *D,

@@ -1,6 +1,8 @@
-// Runtime: module loading, workspace, argument validation, launch
-// sequences (persistent or one-launch-per-step), hipGraph capture and
-// replay, autotuning, and the adjoint pass.
+// Runtime: module loading, argument validation, per-call scratch carved
+// from the caller's workspace, launch sequences (persistent or
+// one-launch-per-step), hipGraph capture and replay, autotuning, and the
+// adjoint pass.  No device memory is allocated here: every buffer a launch
+// touches is the caller's.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -48,7 +50,6 @@ static void drop_graphs(rg_program *p) {
 rg_program::~rg_program() {
     rg::drop_graphs(this);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (ws) (void)hipFree(ws);
     if (module) (void)hipModuleUnload(module);
 }
 
@@ -61,9 +62,6 @@ static rg_status ensure_module(rg_program *p) {
     if (p->module && p->device == dev) return RG_OK;
     if (p->module) {
         drop_graphs(p);
-        if (p->ws) (void)hipFree(p->ws);
-        p->ws = nullptr;
-        p->ws_bytes = 0;
         (void)hipModuleUnload(p->module);
         p->module = nullptr;
         p->kernels.clear();
@@ -115,21 +113,9 @@ static rg_status check_dev(const void *ptr, size_t bytes, const char *what) {
     return RG_OK;
 }
 
-static rg_status ensure_ws(rg_program *p, size_t bytes) {
-    if (bytes <= p->ws_bytes) return RG_OK;
-    drop_graphs(p);  // captured graphs refer to the old workspace
-    if (p->ws) HIPCHK(hipFree(p->ws));
-    p->ws = nullptr;
-    p->ws_bytes = 0;
-    size_t want = std::max<size_t>(bytes, 1 << 20);
-    if (hipMalloc(&p->ws, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(RG_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
-    }
-    p->ws_bytes = want;
-    return RG_OK;
-}
-
+// Sub-buffers of the caller's workspace, each starting 256 bytes past a
+// multiple of 256 from the workspace base.  With base == nullptr only the
+// total size is computed (the pointers handed out are then not used).
 struct Carve {
     char *base;
     size_t off = 0;
@@ -141,6 +127,16 @@ struct Carve {
         return r;
     }
 };
+
+// The workspace must hold `need` bytes (a size query the caller made with
+// rg_workspace_size / rg_adjoint_workspace_size) and be device memory.
+static rg_status check_ws(void *ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return RG_OK;
+    if (!ws || ws_bytes < need)
+        return fail(RG_EINVAL, "workspace of " + std::to_string(need) + " bytes needed (" +
+                                   std::to_string(ws ? ws_bytes : 0) + " given); query it with the workspace-size call");
+    return check_dev(ws, need, "workspace");
+}
 
 struct Launch {
     const char *name;
@@ -225,7 +221,11 @@ static rg_status occupancy_grid(rg_program *p, const char *name, int block, long
 
 // ------------------------------------------------------------ validation --
 
-static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
+// Checks d and fills the launch arguments.  ckpt_optional: checkpoints may
+// be NULL (the adjoint then runs the forward itself); ws: the workspace the
+// call will use (may not overlap any other buffer), ws_bytes its size.
+static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a, bool ckpt_optional,
+                          const void *ws, size_t ws_bytes) {
     const uint32_t dim = p->dim, ny = 2 * dim;
     const size_t n = d.n_rays;
     if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
@@ -280,7 +280,8 @@ static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
         }
         if (d.checkpoint_every > 0) {
             size_t nc = ((size_t)d.n_steps + d.checkpoint_every - 1) / d.checkpoint_every;
-            RGCHK(check_dev(d.checkpoints, 8 * nc * (ny + 1) * n, "checkpoints"));
+            if (d.checkpoints || !ckpt_optional)
+                RGCHK(check_dev(d.checkpoints, 8 * nc * (ny + 1) * n, "checkpoints"));
             a.ckpt_every = d.checkpoint_every;
             a.ckpt = d.checkpoints;
         }
@@ -311,7 +312,8 @@ static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a) {
                          {d.integrator == RG_DOPRI54 ? d.attempts_out : nullptr, 4 * n, "attempts_out"},
                          {ns ? d.traj : nullptr, 8 * ns * 2 * dim * n, "traj"},
                          {ns ? d.traj_D : nullptr, 8 * ns * n, "traj_D"},
-                         {nc ? d.checkpoints : nullptr, 8 * nc * (2 * dim + 1) * n, "checkpoints"}};
+                         {nc ? d.checkpoints : nullptr, 8 * nc * (2 * dim + 1) * n, "checkpoints"},
+                         {ws, ws_bytes, "workspace"}};
     auto overlap = [](const Range &u, const Range &v) {
         if (!u.p || !v.p || !u.bytes || !v.bytes) return false;
         const char *a0 = (const char *)u.p, *b0 = (const char *)v.p;
@@ -394,9 +396,8 @@ static rg_status persistent_rk4_seq(rg_program *p, const rg_kargs &a, int block,
     return RG_OK;
 }
 
+// a.queue: the refill counter in the caller's workspace (carve_trace)
 static rg_status dopri_seq(rg_program *p, rg_kargs a, int block, int compact, std::vector<Launch> &seq) {
-    Carve c{(char *)p->ws};
-    a.queue = c.take<unsigned long long>(1);
     a.compact = compact;
     rg_kargs f;
     std::memset(&f, 0, sizeof f);
@@ -507,13 +508,62 @@ static rg_status tune_dopri(rg_program *p, const rg_kargs &a, hipStream_t s, Tun
 
 // ----------------------------------------------------------------- trace --
 
+// Per-call scratch of each launch form, carved from the workspace: the
+// plain RK4 form's per-ray t, status and step count; the Dormand-Prince
+// refill queue; the plain Dormand-Prince form's per-ray state.  Persistent
+// RK4 keeps everything in registers and needs none.
+static void carve_trace(const rg_trace_desc &d, uint32_t ny, rg_kargs &a, Carve &c) {
+    const long long n = a.n;
+    if (d.integrator == RG_RK4 && d.mode == RG_PERSISTENT) return;
+    if (d.integrator == RG_RK4) {
+        a.s_t = c.take<double>(n);
+        a.s_st = c.take<int>(n);
+        a.s_acc = c.take<int>(n);
+        return;
+    }
+    if (d.mode == RG_PERSISTENT) {
+        a.queue = c.take<unsigned long long>(1);
+        return;
+    }
+    a.s_y = c.take<double>(ny * n);
+    a.s_k1 = c.take<double>(ny * n);
+    a.s_t = c.take<double>(n);
+    a.s_h = c.take<double>(n);
+    a.s_fm = c.take<double>(n);
+    a.s_st = c.take<int>(n);
+    a.s_acc = c.take<int>(n);
+    a.s_att = c.take<int>(n);
+    a.counter = c.take<int>(2);
+}
+
+static size_t trace_ws_bytes(const rg_program *p, const rg_trace_desc &d) {
+    if (d.n_rays == 0) return 0;
+    rg_kargs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = d.n_rays;
+    Carve c{nullptr};
+    carve_trace(d, 2 * p->dim, a, c);
+    return c.off;
+}
+
+rg_status workspace_size(rg_program *p, const rg_trace_desc &d, size_t *bytes) {
+    if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
+    *bytes = trace_ws_bytes(p, d);
+    return RG_OK;
+}
+
 rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
     RGCHK(ensure_module(p));
     rg_kargs a;
-    RGCHK(validate(p, d, a));
+    if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
+    const size_t need = trace_ws_bytes(p, d);
+    RGCHK(validate(p, d, a, false, need ? d.workspace : nullptr, need));
     if (d.n_rays == 0) return RG_OK;
+    RGCHK(check_ws(d.workspace, d.workspace_bytes, need));
     const long long n = a.n;
     const uint32_t ny = 2 * p->dim;
+    Carve cw{(char *)d.workspace};
+    carve_trace(d, ny, a, cw);
     p->last = rg_launch_info{};
     p->last.struct_size = sizeof(rg_launch_info);
     const bool graph = d.use_hipgraph != 0;
@@ -532,11 +582,6 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
     }
     if (d.integrator == RG_RK4) {  // plain: one launch per step
         int block = d.block ? d.block : 256;
-        RGCHK(ensure_ws(p, 3 * 256 + 16 * (size_t)n + 256));
-        Carve c{(char *)p->ws};
-        a.s_t = c.take<double>(n);
-        a.s_st = c.take<int>(n);
-        a.s_acc = c.take<int>(n);
         std::vector<Launch> seq;
         unsigned grid = cdiv(n, block);
         seq.push_back(Launch{"rg_rk4_plain_init", grid, (unsigned)block, a});
@@ -554,7 +599,6 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
         return run_seq(p, seq, graph, s);
     }
     if (d.mode == RG_PERSISTENT) {
-        RGCHK(ensure_ws(p, 4096));
         TuneEntry te;
         if (d.block == 0 || d.compact_interval == 0) RGCHK(tune_dopri(p, a, s, &te));
         int block = d.block ? d.block : te.block;
@@ -568,18 +612,6 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
     }
     // plain adaptive: one attempt per launch, alive count read back every 64 launches
     int block = d.block ? d.block : 256;
-    size_t need = 8 * 256 + (size_t)n * (16 * ny + 3 * 8 + 3 * 4) + 64;
-    RGCHK(ensure_ws(p, need));
-    Carve c{(char *)p->ws};
-    a.s_y = c.take<double>(ny * n);
-    a.s_k1 = c.take<double>(ny * n);
-    a.s_t = c.take<double>(n);
-    a.s_h = c.take<double>(n);
-    a.s_fm = c.take<double>(n);
-    a.s_st = c.take<int>(n);
-    a.s_acc = c.take<int>(n);
-    a.s_att = c.take<int>(n);
-    a.counter = c.take<int>(2);
     unsigned grid = cdiv(n, block);
     RGCHK(launch_one(p, Launch{"rg_dopri_plain_init", grid, (unsigned)block, a}, s));
     long long maxb = d.max_steps;
@@ -590,9 +622,6 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
         maxb = *std::max_element(hb.begin(), hb.end());
     }
     const long long cap = 4 * std::max<long long>(maxb, 1) + 128;
-    int *host = nullptr;
-    HIPCHK(hipHostMalloc((void **)&host, 8, 0));
-    rg_status st = RG_OK;
     for (long long it = 0; it < cap; it++) {
         const bool check = (it % 64) == 63;
         rg_kargs b = a;
@@ -603,43 +632,150 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
             f.fill_p = (double *)a.counter;
             f.fill_n = 1;
             f.fill_v = 0.0;
-            if ((st = launch_one(p, Launch{"rg_fill_f64", 1, 64, f}, s)) != RG_OK) break;
+            RGCHK(launch_one(p, Launch{"rg_fill_f64", 1, 64, f}, s));
         }
-        if ((st = launch_one(p, Launch{"rg_dopri_plain_step", grid, (unsigned)block, b}, s)) != RG_OK) break;
+        RGCHK(launch_one(p, Launch{"rg_dopri_plain_step", grid, (unsigned)block, b}, s));
         if (check) {
-            hipError_t e = hipMemcpyAsync(host, a.counter, 4, hipMemcpyDeviceToHost, s);
+            int alive = 0;  // pageable host memory: the copy completes before the synchronisation returns
+            hipError_t e = hipMemcpyAsync(&alive, a.counter, 4, hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) { st = fail(RG_EHIP, std::string("plain DOPRI readback: ") + hipGetErrorString(e)); break; }
-            if (host[0] == 0) break;
+            if (e != hipSuccess) return fail(RG_EHIP, std::string("plain DOPRI readback: ") + hipGetErrorString(e));
+            if (alive == 0) break;
         }
     }
-    (void)hipHostFree(host);
     p->last.block = block;
     p->last.rays_per_lane = 1;
     p->last.grid = (int)grid;
-    return st;
+    return RG_OK;
 }
 
 // --------------------------------------------------------------- adjoint --
 
-rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
-    RGCHK(ensure_module(p));
+// Workspace of the adjoint: [internal forward: checkpoints, endpoints, step
+// counts and that trace's own scratch] [segment buffer] [gradient partials].
+struct AdjPlan {
+    bool internal_fwd = false;  // fwd->checkpoints == NULL: the forward runs inside the call
+    int block = 0;
+    unsigned grid = 0;          // workgroups of the reverse launch(es)
+    long long lanes = 0;        // per-lane segment buffer rows (persistent) or n (plain)
+    int stride = 0;             // gradient slots per workgroup partial
+    int ns_kept = 0;            // stage states per step in the segment buffer
+};
+
+static rg_status adj_plan(rg_program *p, const rg_trace_desc &d, AdjPlan *pl) {
+    const long long n = d.n_rays;
+    pl->internal_fwd = d.checkpoints == nullptr;
+    pl->block = d.block > 0 && d.block < kAdjointBlock ? d.block : kAdjointBlock;
+    pl->stride = (int)(p->grad_param.size() + (size_t)p->spl_total);
+    pl->ns_kept = p->adj_recompute ? 1 : 4;
+    if (d.mode == RG_PLAIN) {
+        pl->grid = cdiv(n, pl->block);
+        pl->lanes = n;
+    } else {
+        RGCHK(occupancy_grid(p, "rg_rk4_adjoint", pl->block, (long long)cdiv(n, pl->block), &pl->grid));
+        pl->lanes = (long long)pl->grid * pl->block;
+    }
+    return RG_OK;
+}
+
+// Carves the adjoint's buffers.  fd receives the internal forward's
+// description when the plan has one.
+static void carve_adjoint(rg_program *p, const rg_trace_desc &d, const AdjPlan &pl, rg_kargs &a,
+                          rg_trace_desc &fd, Carve &c) {
+    const long long n = d.n_rays;
+    const uint32_t dim = p->dim, ny = 2 * dim;
+    if (pl.internal_fwd) {
+        fd = d;
+        const size_t nc = ((size_t)d.n_steps + d.checkpoint_every - 1) / d.checkpoint_every;
+        fd.checkpoints = c.take<double>(nc * (ny + 1) * n);
+        fd.x_out = c.take<double>(dim * n);
+        fd.k_out = c.take<double>(dim * n);
+        fd.steps_out = c.take<int>(n);
+        fd.t_out = nullptr;
+        fd.status_out = nullptr;
+        fd.store_every = 0;
+        fd.traj = nullptr;
+        fd.traj_D = nullptr;
+        fd.use_hipgraph = 0;
+        fd.workspace_bytes = trace_ws_bytes(p, fd);
+        fd.workspace = fd.workspace_bytes ? c.take<char>(fd.workspace_bytes) : nullptr;
+        a.ckpt = fd.checkpoints;
+        a.steps_out = fd.steps_out;
+    }
+    const size_t seg = (size_t)d.checkpoint_every * (pl.ns_kept * ny + 1) * pl.lanes;
+    a.scratch = c.take<double>(seg);
+    a.scratch_lanes = pl.lanes;
+    if (d.mode == RG_PLAIN) {
+        a.s_y = c.take<double>(ny * n);
+        a.s_lam = c.take<double>(ny * n);
+        a.s_t = c.take<double>(n);
+    }
+    a.gpart = pl.stride > 0 ? c.take<double>((size_t)pl.grid * pl.stride) : nullptr;
+    a.n_part = (int)pl.grid;
+    a.part_stride = pl.stride;
+}
+
+static rg_status adj_check(rg_program *p, const rg_adjoint_desc &ad) {
     if (!p->has_vjp) return fail(RG_ESTATE, "program compiled without want_adjoint");
     if (ad.struct_size < sizeof(rg_adjoint_desc)) return fail(RG_EINVAL, "rg_adjoint_desc.struct_size too small");
     if (!ad.fwd) return fail(RG_EINVAL, "adjoint needs the forward description");
     const rg_trace_desc &d = *ad.fwd;
+    if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
     if (d.integrator != RG_RK4) return fail(RG_EUNSUPPORTED, "adjoint is implemented for RK4");
-    if (d.checkpoint_every <= 0 || !d.checkpoints || !d.steps_out)
-        return fail(RG_ESTATE, "adjoint needs the forward checkpoints and steps_out");
-    rg_kargs a;
-    RGCHK(validate(p, d, a));
+    if (d.precision != RG_FP64) return fail(RG_EUNSUPPORTED, "adjoint is implemented in FP64");
+    if (d.checkpoint_every <= 0) return fail(RG_ESTATE, "adjoint needs fwd->checkpoint_every > 0");
+    if (d.checkpoints && !d.steps_out)
+        return fail(RG_ESTATE, "adjoint on stored checkpoints needs the forward's steps_out");
+    return RG_OK;
+}
+
+static rg_status adjoint_bytes(rg_program *p, const rg_trace_desc &d, size_t *bytes) {
+    *bytes = 0;
     if (d.n_rays == 0) return RG_OK;
+    AdjPlan pl;
+    RGCHK(adj_plan(p, d, &pl));
+    rg_kargs a;
+    std::memset(&a, 0, sizeof a);
+    rg_trace_desc fd;
+    Carve c{nullptr};
+    carve_adjoint(p, d, pl, a, fd, c);
+    *bytes = c.off;
+    return RG_OK;
+}
+
+rg_status adjoint_workspace_size(rg_program *p, const rg_adjoint_desc &ad, size_t *bytes) {
+    RGCHK(ensure_module(p));
+    RGCHK(adj_check(p, ad));
+    return adjoint_bytes(p, *ad.fwd, bytes);
+}
+
+rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    RGCHK(adj_check(p, ad));
+    const rg_trace_desc &d = *ad.fwd;
+    size_t need = 0;
+    RGCHK(adjoint_bytes(p, d, &need));
+    rg_kargs a;
+    RGCHK(validate(p, d, a, true, need ? ad.workspace : nullptr, need));
+    if (d.n_rays == 0) return RG_OK;
+    RGCHK(check_ws(ad.workspace, ad.workspace_bytes, need));
     const long long n = a.n;
-    const uint32_t dim = p->dim, ny = 2 * dim;
+    const uint32_t dim = p->dim;
     RGCHK(check_dev(ad.dL_dx_end, 8 * dim * n, "dL_dx_end"));
     if (ad.dL_dk_end) RGCHK(check_dev(ad.dL_dk_end, 8 * dim * n, "dL_dk_end"));
     if (ad.dL_dx0) RGCHK(check_dev(ad.dL_dx0, 8 * dim * n, "dL_dx0"));
     if (ad.dL_dk0) RGCHK(check_dev(ad.dL_dk0, 8 * dim * n, "dL_dk0"));
+    // the workspace is written before the seeds are read
+    {
+        const char *w0 = (const char *)ad.workspace;
+        const std::pair<const void *, size_t> bufs[] = {{ad.dL_dx_end, 8 * dim * n}, {ad.dL_dk_end, 8 * dim * n},
+                                                        {ad.dL_dx0, 8 * dim * n}, {ad.dL_dk0, 8 * dim * n}};
+        for (const auto &b : bufs) {
+            const char *b0 = (const char *)b.first;
+            if (b0 && need && w0 < b0 + b.second && b0 < w0 + need)
+                return fail(RG_EINVAL, "workspace overlaps an adjoint seed or gradient buffer");
+        }
+    }
     for (uint32_t i = 0; i < p->n_params; i++)
         if (ad.dL_dparams && ad.dL_dparams[i]) {
             RGCHK(check_dev(ad.dL_dparams[i], 8 * (size_t)p->param_len[i], "dL_dparams[i]"));
@@ -650,9 +786,15 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     a.gx0 = ad.dL_dx0;
     a.gk0 = ad.dL_dk0;
 
-    const int block = d.block > 0 && d.block < kAdjointBlock ? d.block : kAdjointBlock;
-    const int stride = (int)(p->grad_param.size() + (size_t)p->spl_total);
-    const int ns_kept = p->adj_recompute ? 1 : 4;  // stage states per step in the segment buffer
+    AdjPlan pl;
+    RGCHK(adj_plan(p, d, &pl));
+    rg_trace_desc fd;
+    Carve cw{(char *)ad.workspace};
+    carve_adjoint(p, d, pl, a, fd, cw);
+    if (pl.internal_fwd) RGCHK(trace(p, fd, s));  // checkpoints and step counts into the workspace
+    const int block = pl.block;
+    const unsigned grid = pl.grid;
+    const int stride = pl.stride;
     // zero the parameter gradients that will be written
     for (uint32_t i = 0; i < p->n_params; i++)
         if (a.dparams[i]) {
@@ -666,18 +808,6 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
 
     if (d.mode == RG_PLAIN) {
         // one launch per step, per-ray state and adjoint in the workspace
-        const unsigned grid = cdiv(n, block);
-        const size_t seg = (size_t)d.checkpoint_every * (ns_kept * ny + 1) * n;
-        const size_t gpart = (size_t)grid * stride;
-        RGCHK(ensure_ws(p, 8 * (seg + 2 * ny * (size_t)n + (size_t)n + gpart) + 1024));
-        Carve c{(char *)p->ws};
-        a.scratch = c.take<double>(seg);
-        a.s_y = c.take<double>(ny * n);
-        a.s_lam = c.take<double>(ny * n);
-        a.s_t = c.take<double>(n);
-        a.gpart = stride > 0 ? c.take<double>(gpart) : nullptr;
-        a.n_part = (int)grid;
-        a.part_stride = stride;
         std::vector<Launch> seq;
         seq.push_back(Launch{"rg_adjp_init", grid, (unsigned)block, a});
         const int ce = d.checkpoint_every;
@@ -705,19 +835,6 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
         return RG_OK;
     }
 
-    unsigned grid;
-    RGCHK(occupancy_grid(p, "rg_rk4_adjoint", block, (long long)cdiv(n, block), &grid));
-    const long long lanes = (long long)grid * block;
-    // per lane and step of a segment: the RK4 stage states kept (1 or 4) and t
-    const size_t scratch = (size_t)d.checkpoint_every * (ns_kept * ny + 1) * lanes;
-    const size_t gpart = (size_t)grid * stride;
-    RGCHK(ensure_ws(p, 8 * (scratch + gpart) + 1024));
-    Carve c{(char *)p->ws};
-    a.scratch = c.take<double>(scratch);
-    a.gpart = stride > 0 ? c.take<double>(gpart) : nullptr;
-    a.scratch_lanes = lanes;
-    a.n_part = (int)grid;
-    a.part_stride = stride;
     RGCHK(launch_one(p, Launch{"rg_rk4_adjoint", grid, (unsigned)block, a}, s));
     if (stride > 0) RGCHK(launch_one(p, Launch{"rg_grad_finalize", cdiv(stride, 256), 256, a}, s));
     p->last.block = block;

@@ -17,6 +17,7 @@ _lib = C.CDLL(LIB_PATH)
 _lib.rg_hand_last_error.restype = C.c_char_p
 _lib.rg_hand_aniso_trace.restype = C.c_int32
 _lib.rg_hand_aniso_adjoint.restype = C.c_int32
+_lib.rg_hand_aniso_adjoint_workspace_size.restype = C.c_int32
 MAXB = 32
 
 
@@ -54,8 +55,24 @@ def trace(hm, x0, k0, omega, s, dt, n_steps, x_out, k_out, ckpt_every=0, ckpt=No
                                   C.c_void_p(rgb._stream_handle(stream))), "rg_hand_aniso_trace")
 
 
-def adjoint(hm, omega, s, dt, n_steps, ckpt_every, ckpt, lx, lk, gx0, gk0, gs, block=0, stream=None):
-    _chk(_lib.rg_hand_aniso_adjoint(C.byref(hm), C.c_uint32(omega.shape[-1]), _p(omega), _p(s),
+def workspace_size(n, ckpt_every, block=0) -> int:
+    b = C.c_size_t()
+    _chk(_lib.rg_hand_aniso_adjoint_workspace_size(C.c_uint32(n), C.c_int32(ckpt_every), C.c_int32(block),
+                                                   C.byref(b)), "rg_hand_aniso_adjoint_workspace_size")
+    return int(b.value)
+
+
+def adjoint(hm, omega, s, dt, n_steps, ckpt_every, ckpt, lx, lk, gx0, gk0, gs, block=0, stream=None,
+            workspace=None):
+    """The workspace (a torch uint8 tensor of at least workspace_size bytes)
+    is allocated here when not given."""
+    import torch
+    n = int(omega.shape[-1])
+    if workspace is None:
+        workspace = torch.empty(max(1, workspace_size(n, ckpt_every, block)), dtype=torch.uint8,
+                                device=omega.device)
+    _chk(_lib.rg_hand_aniso_adjoint(C.byref(hm), C.c_uint32(n), _p(omega), _p(s),
                                     C.c_double(dt), C.c_int32(n_steps), C.c_int32(ckpt_every), _p(ckpt),
                                     _p(lx), _p(lk), _p(gx0), _p(gk0), _p(gs), C.c_int32(block),
+                                    _p(workspace), C.c_size_t(workspace.numel()),
                                     C.c_void_p(rgb._stream_handle(stream))), "rg_hand_aniso_adjoint")

@@ -63,7 +63,7 @@ SYMBOLS = [
     "rg_df", "rg_node_get", "rg_graph_size", "rg_eval", "rg_node_to_string", "rg_compile",
     "rg_destroy_program", "rg_program_info_get", "rg_program_source", "rg_program_functions",
     "rg_trace_rays", "rg_trace_rays_adjoint", "rg_eval_rays", "rg_last_launch", "rg_last_error",
-    "rg_solve_k",
+    "rg_solve_k", "rg_workspace_size", "rg_adjoint_workspace_size",
 ]
 
 
@@ -112,13 +112,15 @@ class TraceDesc(C.Structure):
                 ("checkpoint_every", C.c_int32), ("checkpoints", C.c_void_p),
                 ("mode", C.c_int32), ("use_hipgraph", C.c_int32), ("block", C.c_int32),
                 ("rays_per_lane", C.c_int32), ("compact_interval", C.c_int32),
-                ("attempts_out", C.c_void_p), ("precision", C.c_int32)]
+                ("attempts_out", C.c_void_p), ("precision", C.c_int32),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 class AdjointDesc(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("fwd", C.POINTER(TraceDesc)),
                 ("dL_dx_end", C.c_void_p), ("dL_dk_end", C.c_void_p), ("dL_dx0", C.c_void_p),
-                ("dL_dk0", C.c_void_p), ("dL_dparams", C.c_void_p)]
+                ("dL_dk0", C.c_void_p), ("dL_dparams", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 class SolveDesc(C.Structure):
@@ -387,7 +389,8 @@ class Program:
                   t0=None, store_every=0, traj=None, traj_D=None, x_out=None, k_out=None,
                   t_out=None, status_out=None, steps_out=None, checkpoint_every=0,
                   checkpoints=None, mode=PERSISTENT, use_hipgraph=False, block=0,
-                  rays_per_lane=0, compact_interval=0, attempts_out=None, precision=FP64):
+                  rays_per_lane=0, compact_interval=0, attempts_out=None, precision=FP64,
+                  workspace=None):
         import torch
         f64, i32 = torch.float64, torch.int32
         for t, nm, dt_ in ((x0, "x0", f64), (k0, "k0", f64), (omega, "omega", f64), (t0, "t0", f64),
@@ -423,13 +426,37 @@ class Program:
         d.block, d.rays_per_lane, d.compact_interval = int(block), int(rays_per_lane), int(compact_interval)
         d.attempts_out = _dptr(attempts_out)
         d.precision = int(precision)
+        # per-call scratch: a torch allocation of the size the library asks for
+        if d.n_rays > 0:
+            need = self.workspace_size(d)
+            if need > 0:
+                if workspace is None:
+                    workspace = torch.empty(need, dtype=torch.uint8, device=x0.device)
+                _check_tensor(workspace, "workspace")
+                d.workspace, d.workspace_bytes = _dptr(workspace), workspace.numel() * workspace.element_size()
+                d._ws = workspace
         return d
+
+    def workspace_size(self, d: TraceDesc) -> int:
+        """Bytes of device workspace rg_trace_rays needs for d."""
+        b = C.c_size_t()
+        _chk(_lib.rg_workspace_size(self.h, C.byref(d), C.byref(b)), "rg_workspace_size")
+        return int(b.value)
+
+    def adjoint_workspace_size(self, a: "AdjointDesc") -> int:
+        b = C.c_size_t()
+        _chk(_lib.rg_adjoint_workspace_size(self.h, C.byref(a), C.byref(b)), "rg_adjoint_workspace_size")
+        return int(b.value)
 
     def trace_desc(self, d: TraceDesc, stream=None):
         _chk(_lib.rg_trace_rays(self.h, C.byref(d), C.c_void_p(_stream_handle(stream))), "rg_trace_rays")
 
     def adjoint_desc(self, fwd: TraceDesc, dL_dx_end, dL_dk_end=None, dL_dx0=None, dL_dk0=None,
-                     dL_dparams=(), stream=None):
+                     dL_dparams=(), stream=None, workspace=None):
+        """Adjoint of the trace described by fwd.  The workspace (a torch
+        allocation of the size the library reports) is kept on fwd and reused
+        by later calls that need no more."""
+        import torch
         for t, nm in ((dL_dx_end, "dL_dx_end"), (dL_dk_end, "dL_dk_end"), (dL_dx0, "dL_dx0"),
                       (dL_dk0, "dL_dk0")):
             _check_tensor(t, nm)
@@ -442,6 +469,17 @@ class Program:
         gpa = (C.c_void_p * max(1, len(gp)))(*[_dptr(g) for g in gp])
         a._keep = gpa
         a.dL_dparams = C.cast(gpa, C.c_void_p).value if gp else None
+        if fwd.n_rays > 0:
+            need = self.adjoint_workspace_size(a)
+            if need > 0:
+                if workspace is None:
+                    workspace = getattr(fwd, "_adj_ws", None)
+                    if workspace is None or workspace.numel() < need:
+                        fwd._adj_ws = None
+                        workspace = torch.empty(need, dtype=torch.uint8, device=dL_dx_end.device)
+                        fwd._adj_ws = workspace
+                _check_tensor(workspace, "workspace")
+                a.workspace, a.workspace_bytes = _dptr(workspace), workspace.numel() * workspace.element_size()
         _chk(_lib.rg_trace_rays_adjoint(self.h, C.byref(a), C.c_void_p(_stream_handle(stream))),
              "rg_trace_rays_adjoint")
 
