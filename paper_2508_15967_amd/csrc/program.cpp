@@ -342,8 +342,10 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     I.rhs_flops_issued = fl_rhs.issued;
     I.rhs_flops_ray_invariant = fl_rhs.inv_alg;
     // RK4 update: per component 3 stage fma + fma, fma, add + final fma = 13
-    // flops, plus t += dt and the two step constants.
-    const double upd = 13.0 * ny + 1.0;
+    // flops, plus t += dt (the two step constants are computed once per
+    // launch).  Components whose right-hand side is identically zero keep
+    // their value and cost nothing (rg_rk4_step skips them).
+    const double upd = 13.0 * (ny - __builtin_popcount(zero_mask)) + 1.0;
     I.rk4_step_flops_alg = 4 * fl_rhs.alg + upd;
     I.rk4_step_flops_issued = 4 * fl_rhs.issued + upd;
     // DOPRI attempt: 6 new right-hand sides; stage sums 2s+1 flops per
