@@ -270,6 +270,34 @@ typedef struct {
  * rg_workspace_size reports is RG_EINVAL. */
 rg_status rg_trace_rays(rg_program *p, const rg_trace_desc *d, void *hip_stream);
 
+/* Loads the program's code object on the current device and prepares the
+ * device for rg_trace_rays_noalloc (resolves the address of the library's
+ * static scratch array there).  Once per device, before the first
+ * rg_trace_rays_noalloc on it; the other entry points load on first use. */
+rg_status rg_program_load(rg_program *p);
+
+/* rg_trace_rays for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same trace, inputs and outputs as rg_trace_rays (results bitwise equal),
+ * but nothing in the call allocates.  Its per-call scratch (the
+ * Dormand-Prince refill queue, the per-ray state of the one-launch-per-step
+ * forms) comes from a static device array of RG_NOALLOC_SCRATCH_BYTES = 4 MiB
+ * per device, held by the library until the process ends; d->workspace is
+ * ignored.  Limits and rules:
+ *   - rg_program_load must have run on the current device (RG_ESTATE);
+ *   - a trace needing more scratch than the array holds is RG_EINVAL
+ *     (rg_workspace_size tells: persistent RK4 needs none, persistent
+ *     Dormand-Prince 8 bytes, the plain forms 16 (RK4) or 144
+ *     (Dormand-Prince, 3-D) bytes per ray);
+ *   - launch parameters must be given (block; rays_per_lane for RK4;
+ *     compact_interval for Dormand-Prince): no autotuning (RG_EINVAL);
+ *   - use_hipgraph must be 0: the launches are issued directly (RG_EINVAL).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (what must start at zero is cleared by a kernel inside the call):
+ * calls that overlap in time on one device, on any streams, race and give
+ * wrong results. */
+rg_status rg_trace_rays_noalloc(rg_program *p, const rg_trace_desc *d, void *hip_stream);
+
 /* Device workspace, in bytes, that rg_trace_rays needs for description d
  * (its workspace fields are ignored).  Depends on the integrator, the mode
  * and n_rays; 0 for persistent RK4.  Loads the program's code object on the

@@ -271,6 +271,20 @@ rg_status rg_trace_rays_adjoint(rg_program *p, const rg_adjoint_desc *d, void *s
     GUARD_END
 }
 
+rg_status rg_program_load(rg_program *p) {
+    if (!p) return fail(RG_EINVAL, "NULL argument");
+    GUARD_BEGIN
+    return rg::program_load(p);
+    GUARD_END
+}
+
+rg_status rg_trace_rays_noalloc(rg_program *p, const rg_trace_desc *d, void *stream) {
+    if (!p || !d) return fail(RG_EINVAL, "NULL argument");
+    GUARD_BEGIN
+    return rg::trace_noalloc(p, *d, (hipStream_t)stream);
+    GUARD_END
+}
+
 rg_status rg_workspace_size(rg_program *p, const rg_trace_desc *d, size_t *bytes) {
     if (!p || !d || !bytes) return fail(RG_EINVAL, "NULL argument");
     GUARD_BEGIN

@@ -70,6 +70,8 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
 rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s);
 rg_status adjoint(rg_program *p, const rg_adjoint_desc &d, hipStream_t s);
 rg_status workspace_size(rg_program *p, const rg_trace_desc &d, size_t *bytes);
+rg_status program_load(rg_program *p);
+rg_status trace_noalloc(rg_program *p, const rg_trace_desc &d, hipStream_t s);
 rg_status adjoint_workspace_size(rg_program *p, const rg_adjoint_desc &d, size_t *bytes);
 rg_status solve_k(rg_program *p, const rg_solve_desc &d, hipStream_t s);
 rg_status eval_points(rg_program *p, uint32_t n, const double *y, const double *omega,

@@ -14,6 +14,7 @@
 #include <fstream>
 #include <sstream>
 
+#include "noalloc.hpp"
 #include "program.hpp"
 
 namespace rg {
@@ -552,14 +553,16 @@ rg_status workspace_size(rg_program *p, const rg_trace_desc &d, size_t *bytes) {
     return RG_OK;
 }
 
-rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
+// static_ws: d.workspace is the library's static scratch (its size was
+// checked by the caller; it is not a runtime allocation to be queried).
+static rg_status trace_impl(rg_program *p, const rg_trace_desc &d, hipStream_t s, bool static_ws) {
     RGCHK(ensure_module(p));
     rg_kargs a;
     if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
     const size_t need = trace_ws_bytes(p, d);
     RGCHK(validate(p, d, a, false, need ? d.workspace : nullptr, need));
     if (d.n_rays == 0) return RG_OK;
-    RGCHK(check_ws(d.workspace, d.workspace_bytes, need));
+    if (!static_ws) RGCHK(check_ws(d.workspace, d.workspace_bytes, need));
     const long long n = a.n;
     const uint32_t ny = 2 * p->dim;
     Carve cw{(char *)d.workspace};
@@ -647,6 +650,45 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
     p->last.rays_per_lane = 1;
     p->last.grid = (int)grid;
     return RG_OK;
+}
+
+rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) { return trace_impl(p, d, s, false); }
+
+rg_status program_load(rg_program *p) {
+    RGCHK(ensure_module(p));
+    std::string err;
+    if (noalloc_resolve(p->device, &err) != 0) return fail(RG_EHIP, err);
+    return RG_OK;
+}
+
+// rg_trace_rays with the per-call scratch taken from the static device
+// array instead of d.workspace, and nothing else that allocates: the code
+// object must already be loaded on the current device (program_load), the
+// launch parameters must be given (the autotuner creates events) and the
+// launch sequence runs directly (instantiating a hipGraph allocates).
+rg_status trace_noalloc(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
+    if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
+    if (p->compile_only) return fail(RG_ESTATE, "program was compiled with compile_only=1");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    void *scr = noalloc_address(dev);
+    if (!p->module || p->device != dev || !scr)
+        return fail(RG_ESTATE, "rg_trace_rays_noalloc: call rg_program_load on this device first");
+    if (d.use_hipgraph) return fail(RG_EINVAL, "rg_trace_rays_noalloc: use_hipgraph must be 0");
+    const bool persistent = d.mode == RG_PERSISTENT;
+    if (persistent && (d.block == 0 || (d.integrator == RG_RK4 && d.precision == RG_FP64 && d.rays_per_lane == 0) ||
+                       (d.integrator == RG_DOPRI54 && d.compact_interval == 0)))
+        return fail(RG_EINVAL, "rg_trace_rays_noalloc: block, rays_per_lane (RK4) and compact_interval "
+                               "(Dormand-Prince) must be given (no autotuning)");
+    const size_t need = trace_ws_bytes(p, d);
+    if (need > RG_NOALLOC_SCRATCH_BYTES)
+        return fail(RG_EINVAL, "rg_trace_rays_noalloc: this trace needs " + std::to_string(need) +
+                                   " bytes of scratch, more than the static " +
+                                   std::to_string((size_t)RG_NOALLOC_SCRATCH_BYTES));
+    rg_trace_desc dd = d;
+    dd.workspace = need ? scr : nullptr;
+    dd.workspace_bytes = need ? RG_NOALLOC_SCRATCH_BYTES : 0;
+    return trace_impl(p, dd, s, true);
 }
 
 // --------------------------------------------------------------- adjoint --

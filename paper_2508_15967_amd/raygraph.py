@@ -63,7 +63,8 @@ SYMBOLS = [
     "rg_df", "rg_node_get", "rg_graph_size", "rg_eval", "rg_node_to_string", "rg_compile",
     "rg_destroy_program", "rg_program_info_get", "rg_program_source", "rg_program_functions",
     "rg_trace_rays", "rg_trace_rays_adjoint", "rg_eval_rays", "rg_last_launch", "rg_last_error",
-    "rg_solve_k", "rg_workspace_size", "rg_adjoint_workspace_size",
+    "rg_solve_k", "rg_workspace_size", "rg_adjoint_workspace_size", "rg_program_load",
+    "rg_trace_rays_noalloc",
 ]
 
 
@@ -447,6 +448,16 @@ class Program:
         b = C.c_size_t()
         _chk(_lib.rg_adjoint_workspace_size(self.h, C.byref(a), C.byref(b)), "rg_adjoint_workspace_size")
         return int(b.value)
+
+    def load(self):
+        """Load the code object on the current device (rg_program_load)."""
+        _chk(_lib.rg_program_load(self.h), "rg_program_load")
+
+    def trace_desc_noalloc(self, d: TraceDesc, stream=None):
+        """rg_trace_rays_noalloc: scratch from the library's static device
+        array (d.workspace is ignored); launch parameters must be given."""
+        _chk(_lib.rg_trace_rays_noalloc(self.h, C.byref(d), C.c_void_p(_stream_handle(stream))),
+             "rg_trace_rays_noalloc")
 
     def trace_desc(self, d: TraceDesc, stream=None):
         _chk(_lib.rg_trace_rays(self.h, C.byref(d), C.c_void_p(_stream_handle(stream))), "rg_trace_rays")
