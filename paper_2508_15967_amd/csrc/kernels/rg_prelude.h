@@ -16,15 +16,19 @@ struct rg_P {
 
 // 1/d: the hardware reciprocal estimate refined by two Newton steps
 // r <- r + r (1 - d r), within one ulp of 1/d for normal finite d (the
-// correctly rounded division takes about twice the instructions).  d = 0,
-// +-inf and subnormal d give a non-finite result instead of +-inf / 0.
+// correctly rounded division takes about twice the instructions).  The
+// Newton steps turn the estimate's exact special values into NaN (at d = 0
+// the estimate is inf and d r = 0 inf); the division fix-up instruction
+// puts back the IEEE result of 1/d for zero, infinite and NaN d and for
+// quotients that overflow or underflow, and passes r through otherwise.
 RG_FN double rg_rcp(double d) {
 #if defined(__HIP_DEVICE_COMPILE__)
     double r = __builtin_amdgcn_rcp(d);
     double e = fma(-d, r, 1.0);
     r = fma(e, r, r);
     e = fma(-d, r, 1.0);
-    return fma(e, r, r);
+    r = fma(e, r, r);
+    return __builtin_amdgcn_div_fixup(r, d, 1.0);
 #else
     return 1.0 / d;
 #endif

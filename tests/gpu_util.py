@@ -37,12 +37,14 @@ def dev(a, dtype=None):
     return t.cuda()
 
 
-def gpu_trace(w, store=False, store_D=False, checkpoint_every=0, **kw):
+def gpu_trace(w, store=False, store_D=False, checkpoint_every=0, k0=None, **kw):
     """Trace workload w on the GPU through the C ABI; returns numpy arrays
-    (and the torch tensors under '_t')."""
+    (and the torch tensors under '_t').  k0: launch wavevectors already on
+    the device (e.g. from the GPU Newton solve) instead of w.k0."""
     torch = torch_mod()
     _, _, prog, params = program(w, want_adjoint=kw.pop("want_adjoint", False))
-    x0, k0, om = dev(w.x0), dev(w.k0), dev(w.omega)
+    x0, om = dev(w.x0), dev(w.omega)
+    k0 = dev(w.k0) if k0 is None else k0
     pt = [dev(p) for p in params]
     args = dict(integrator=w.integrator, dt=w.dt, n_steps=w.n_steps, h0=w.h0, rtol=w.rtol,
                 atol=w.atol, hmin=w.hmin)
@@ -78,14 +80,54 @@ def traj_errors(tg, to, omega, dim):
     return (dx / nx).max(), (dk / nk).max()
 
 
-def ill_conditioned(oracle, w, thr=1e-12):
+# Largest share of rays a test may set aside as ill-conditioned (observed:
+# none to a few per thousand in the random media of workloads 3 and 5).
+MAX_ILL = 0.01
+ONE_STEP_TOL = 1e-14  # one oracle RK4 step from a GPU state vs the GPU's next state
+
+
+def ill_conditioned(oracle, w, thr=1e-12, **trace_kw):
     """Rays whose oracle trajectory moves by more than thr (relative) when
     the last bit of the initial state is flipped: rounding differences are
-    amplified there, so they are compared by one-step parity instead."""
-    base = oracle.trace(w)
+    amplified there, so the trajectory comparison cannot hold them to 1e-11.
+    RK4 tests check such rays by one_step_parity; Dormand-Prince tests by
+    the free-run criteria (same status, steps within 1 %, endpoints 1e-6)."""
+    base = oracle.trace(w, **trace_kw)
     w2 = w.subset(w.n)
     w2.x0 = np.nextafter(w.x0, np.inf)
     w2.k0 = np.nextafter(w.k0, np.inf)
-    pert = oracle.trace(w2)
+    pert = oracle.trace(w2, **trace_kw)
     ex, ek = ray_errors(pert, base, w.omega, w.dim)
     return np.maximum(ex, ek) > thr, base
+
+
+def one_step_parity(oracle, w, idx, **launch):
+    """For the rays idx of the RK4 workload w: the GPU trace with every state
+    stored, and one oracle RK4 step from each stored state (except the
+    last) compared with the GPU's next stored state.  Returns the largest
+    per-state relative error (norms as in ray_errors); the trajectory as a
+    whole may diverge from the oracle's (ill-conditioned rays), each step
+    may not."""
+    idx = np.asarray(idx)
+    if idx.size == 0:
+        return 0.0
+    ws = w.select(idx)
+    ws.store_every = 1
+    g = gpu_trace(ws, store=True, **launch)
+    traj = g["traj"]                      # [n_steps + 1][2d][m]
+    d, m = w.dim, ws.n
+    live = min(int(g["steps"].min()), ws.n_steps)
+    states = traj[:live]                  # states 0 .. live-1, each followed by a step
+    y = states.transpose(1, 0, 2).reshape(2 * d, -1)
+    one = ws.select(np.zeros(y.shape[1], dtype=np.int64))
+    one.x0 = np.ascontiguousarray(y[:d])
+    one.k0 = np.ascontiguousarray(y[d:])
+    one.omega = np.ascontiguousarray(np.tile(ws.omega, live))
+    one.n_steps = 1
+    one.store_every = 0
+    one.budget = None
+    one.targets = None
+    o = oracle.trace(one)
+    nxt = traj[1:live + 1].transpose(1, 0, 2).reshape(2 * d, -1)
+    ex, ek = ray_errors({"x": nxt[:d], "k": nxt[d:]}, o, one.omega, d)
+    return float(max(ex.max(), ek.max()))

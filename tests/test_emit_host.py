@@ -99,11 +99,19 @@ def _points(w, n, rng):
     return np.ascontiguousarray(y), np.ascontiguousarray(w.omega[idx])
 
 
-@pytest.mark.parametrize("cfg", ["1", "2", "3", "4", "5", "cO", "cX"])
+# cold-plasma media of the tests: electrons only with k perpendicular to B
+# (cO, cX), and with a hydrogen ion species and an oblique n_z (cO2, cX2),
+# where the M13, M23 and n_z terms of the determinant and the ion terms of
+# the species sums (eqs. 6, 8-10) are nonzero
+COLD = {"cO": lambda: W.coldplasma("O"), "cX": lambda: W.coldplasma("X", x0=12.0),
+        "cO2": lambda: W.coldplasma("O", mu=W.MU_H, nz=W.CP_NZ),
+        "cX2": lambda: W.coldplasma("X", x0=12.0, mu=W.MU_H, nz=0.3)}
+
+
+@pytest.mark.parametrize("cfg", ["1", "2", "3", "4", "5", "cO", "cX", "cO2", "cX2"])
 def test_emitted_functions_match_oracle(oracle, cfg):
     from paper_2508_15967_amd import media
-    w = {"cO": lambda: W.coldplasma("O"), "cX": lambda: W.coldplasma("X", x0=12.0)}.get(
-        cfg, lambda: W.make(cfg, 2048))()
+    w = COLD.get(cfg, lambda: W.make(cfg, 2048))()
     g, D, params = media.build(w.medium)
     adj = cfg in ("4", "5")
     prog = g.compile(D, want_adjoint=adj, compile_only=True)
@@ -140,7 +148,7 @@ def test_emitted_functions_match_oracle(oracle, cfg):
             assert np.abs(got - go).max() / np.abs(go).max() < 1e-12
 
 
-@pytest.mark.parametrize("cfg", ["1", "2", "3", "5", "cO", "cX"])
+@pytest.mark.parametrize("cfg", ["1", "2", "3", "5", "cO", "cX", "cO2"])
 def test_emitted_fp32_rhs(oracle, cfg):
     """The single precision right-hand side (same graph, float arithmetic)
     against the oracle's FP64 formulas at the same (float-representable)
@@ -152,8 +160,7 @@ def test_emitted_fp32_rhs(oracle, cfg):
     sum of products several orders of magnitude larger than its value near
     the cutoffs, and its partials lose correspondingly more: 1e-3 there."""
     from paper_2508_15967_amd import media
-    w = {"cO": lambda: W.coldplasma("O"), "cX": lambda: W.coldplasma("X", x0=12.0)}.get(
-        cfg, lambda: W.make(cfg, 2048))()
+    w = COLD.get(cfg, lambda: W.make(cfg, 2048))()
     g, D, params = media.build(w.medium)
     prog = g.compile(D, compile_only=True, fp32=True)
     rng = np.random.default_rng(5)

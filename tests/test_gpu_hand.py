@@ -26,30 +26,45 @@ def _hand_run(w, ckpt=100):
             "gk0": gk0.cpu().numpy(), "gs": gs.cpu().numpy()}
 
 
+def _ray_rel(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+
+
 def test_hand_matches_oracle(oracle):
+    """Every well-conditioned ray (at most 1 % are not) to 1e-11 in the
+    endpoints and 1e-9 per ray in dL/dx0, dL/dk0; each blob-scale gradient
+    to 1e-9 relative to itself."""
     w = W.make("5", 512)
     w.n_steps = 1000
     h = _hand_run(w)
     bad, o = U.ill_conditioned(oracle, w)
+    assert bad.mean() <= U.MAX_ILL
+    ok = ~bad
     ex, ek = U.ray_errors(h, o, w.omega, w.dim)
-    assert ex[~bad].max() < U.TOL and ek[~bad].max() < U.TOL
+    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL
     lam = np.concatenate([2 * (o["x"] - w.targets), np.zeros_like(o["k"])])
     lam0, go = oracle.adjoint(w, lam)
-    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
-    assert rel(h["gk0"], lam0[3:]) < 1e-9 and rel(h["gx0"], lam0[:3]) < 1e-9
-    assert rel(h["gs"], go) < 1e-9
+    assert _ray_rel(h["gk0"], lam0[3:])[ok].max() < 1e-9 and _ray_rel(h["gx0"], lam0[:3])[ok].max() < 1e-9
+    assert (np.abs(h["gs"] - go) / np.maximum(np.abs(go), 1e-6 * np.abs(go).max())).max() < 1e-9
 
 
-def test_compiled_matches_hand():
+def test_compiled_matches_hand(oracle):
     """Graph-generated forward and adjoint against the hand-derived kernels on
-    16,384 rays x 2,000 steps of workload 5."""
+    16,384 rays x 2,000 steps of workload 5: every ray the oracle finds
+    well-conditioned (at most 1 % are not) to 1e-11 in the endpoints and
+    1e-9 per ray in dL/dk0; the blob-scale gradients (sums over all rays,
+    the ill-conditioned ones included) to 1e-8 each."""
     from tests.test_gpu_adjoint import _gpu_grad
     w = W.make("5", 16384)
     w.n_steps = 2000
     h = _hand_run(w)
     g = _gpu_grad(w)
+    bad, _ = U.ill_conditioned(oracle, w)
+    print(f"ill-conditioned: {bad.sum()} of {w.n}", flush=True)
+    assert bad.mean() <= U.MAX_ILL
+    ok = ~bad
     ex = np.linalg.norm(g["x"] - h["x"], axis=0) / np.maximum(np.linalg.norm(h["x"], axis=0), 1)
-    assert np.quantile(ex, 0.99) < 1e-11
-    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
-    assert rel(g["gp"][0], h["gs"]) < 1e-8
-    assert np.quantile(np.abs(g["gk0"] - h["gk0"]).max(0) / np.abs(h["gk0"]).max(0), 0.99) < 1e-9
+    assert ex[ok].max() < 1e-11, ex[ok].max()
+    es = np.abs(g["gp"][0] - h["gs"]) / np.maximum(np.abs(h["gs"]), 1e-6 * np.abs(h["gs"]).max())
+    assert es.max() < 1e-8, es.max()
+    assert _ray_rel(g["gk0"], h["gk0"])[ok].max() < 1e-9

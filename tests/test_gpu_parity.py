@@ -132,6 +132,8 @@ def test_spline_forward(oracle):
 
 
 def test_aniso_forward(oracle):
+    """Every well-conditioned ray to 1e-11; the ill-conditioned ones (at most
+    1 %) step by step from the GPU's own states."""
     w = W.make("5", 1024)
     w.n_steps = 2000
     _print_case("aniso", w)
@@ -139,9 +141,47 @@ def test_aniso_forward(oracle):
     bad, o = U.ill_conditioned(oracle, w)
     ex, ek = U.ray_errors(g, o, w.omega, w.dim)
     ok = ~bad
-    print(f"ill-conditioned rays excluded: {bad.sum()} of {w.n}")
-    assert bad.mean() < 0.05
+    print(f"ill-conditioned rays: {bad.sum()} of {w.n}")
+    assert bad.mean() <= U.MAX_ILL
     assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+    e1 = U.one_step_parity(oracle, w, np.flatnonzero(bad))
+    assert e1 <= U.ONE_STEP_TOL, e1
+
+
+def _dopri_check(oracle, w, g, o, bad, min_same):
+    """Dormand-Prince parity.  Rays whose step sequence matches the oracle's
+    (status, accepted steps, attempts and end time t, which is the sum of
+    the step sizes, all equal) and that are well-conditioned: endpoints to
+    1e-11.  The others -- an accept/reject or step-factor decision taken at
+    a rounding point of err that rounding flips, or an ill-conditioned ray;
+    at most 1 % of the rays -- by the free-run criteria: the same
+    termination reason for all but 0.1 % of all rays, accepted steps within
+    1 % (or one step), and, for the well-conditioned ones, the GPU endpoint
+    on the oracle's trajectory: the oracle integrated (its own controller,
+    no box, no budget) to the GPU ray's end time agrees to 1e-6."""
+    same = ((g["status"] == o["status"]) & (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
+            & (g["t"] == o["t"]))
+    print(f"ill-conditioned: {bad.sum()}, step-sequence mismatches: {(~same).sum()} of {len(same)}", flush=True)
+    assert same.mean() >= min_same and bad.mean() <= U.MAX_ILL
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    ok = same & ~bad
+    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+    assert (g["status"] != o["status"]).mean() <= 1e-3
+    free = ~ok
+    ds = np.abs(g["steps"][free].astype(np.int64) - o["steps"][free])
+    assert np.all(ds <= np.maximum(1, 0.01 * o["steps"][free])), ds.max()
+    worst = 0.0
+    for r in np.flatnonzero(free & ~bad & ~same & (g["status"] != 3) & (g["t"] > 0)):
+        wr = w.select([r])
+        wr.box_lo = wr.box_hi = None
+        wr.hmin = 0.0
+        wr.budget = np.array([1 << 24], dtype=np.int32)
+        orr = oracle.trace(wr, t_end=float(g["t"][r]))
+        assert orr["t"][0] == g["t"][r]
+        e = U.ray_errors({"x": g["x"][:, [r]], "k": g["k"][:, [r]]}, orr, wr.omega, w.dim)
+        worst = max(worst, float(max(e[0][0], e[1][0])))
+    print(f"free-run rays on the oracle's trajectory: max endpoint error {worst:.2e}", flush=True)
+    assert worst <= 1e-6, worst
 
 
 def test_dopri_bumps_subset(oracle):
@@ -151,12 +191,7 @@ def test_dopri_bumps_subset(oracle):
     _print_case("dopri", w)
     g = U.gpu_trace(w)
     bad, o = U.ill_conditioned(oracle, w)
-    same = (g["status"] == o["status"]) & (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
-    print(f"ill-conditioned: {bad.sum()}, status/steps mismatches: {(~same).sum()}")
-    assert same.mean() >= 0.999
-    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
-    ok = same & ~bad
-    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+    _dopri_check(oracle, w, g, o, bad, 0.999)
 
 
 def test_bumps_full_size_sampled(oracle):
@@ -170,16 +205,41 @@ def test_bumps_full_size_sampled(oracle):
     idx = np.sort(np.random.default_rng(41).choice(w.n, 512, replace=False))
     ws = w.select(idx)
     bad, o = U.ill_conditioned(oracle, ws)
-    gs = {k: (g[k][..., idx] if k in ("x", "k", "status", "steps", "attempts") else None)
-          for k in ("x", "k", "status", "steps", "attempts")}
-    same = (gs["status"] == o["status"]) & (gs["steps"] == o["steps"]) & (gs["attempts"] == o["attempts"])
-    print(f"ill-conditioned: {bad.sum()}, status/steps mismatches: {(~same).sum()}", flush=True)
-    assert same.mean() >= 0.99
-    ex, ek = U.ray_errors(gs, o, ws.omega, w.dim)
-    ok = same & ~bad
-    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+    gs = {k: g[k][..., idx] for k in ("x", "k", "status", "steps", "attempts")}
+    gs["t"] = g["t"][idx]
+    _dopri_check(oracle, ws, gs, o, bad, 0.99)
     del g
     torch.cuda.empty_cache()
+
+
+def test_reciprocal_special_values_as_ieee_division(oracle):
+    """The emitted reciprocal of dD/domega at zero, infinite, subnormal and
+    extreme-exponent arguments gives what IEEE division gives (the oracle
+    divides): homogeneous medium, dx/dt = k/(omega N0) with omega = +-0,
+    +-inf, subnormals, 1e-300, 1e300; +-inf, 0 and finite results alike.
+    (Arguments within a factor 2 of the overflow threshold of 1/omega are
+    left out: there the product of k and a reciprocal, which is what the
+    emitted code computes, and the oracle's quotient can fall on different
+    sides of it.)"""
+    torch = U.torch_mod()
+    om = np.array([0.0, -0.0, np.inf, -np.inf, 5e-324, 1e-310, -2e-310, 2.2e-308, 1e-300, 1e300,
+                   1.0, 0.3])
+    n = om.size
+    w = W.homog(n_rays=n, dim=3, N0=1.0)
+    _, _, prog, _ = U.program(w)
+    y = np.concatenate([np.zeros((3, n)), np.tile([[1.0], [-2.0], [0.5]], (1, n))])
+    f, _ = prog.eval(U.dev(y), U.dev(om))
+    torch.cuda.synchronize()
+    got = f.cpu().numpy()[:3]
+    ref, _, _ = oracle.eval_points(w.medium, y, om)
+    ref = ref[:3]
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isnan(got), np.isnan(ref)), (got, ref)
+    assert np.array_equal(got[~fin & ~np.isnan(ref)], ref[~fin & ~np.isnan(ref)])
+    assert np.array_equal(np.signbit(got[ref == 0]), np.signbit(ref[ref == 0]))
+    big = fin & (np.abs(ref) > 1e-300)
+    rel = np.abs(got[big] - ref[big]) / np.abs(ref[big])
+    assert rel.max() <= 4e-16, rel.max()
 
 
 def test_reciprocal_within_one_ulp():

@@ -90,6 +90,10 @@ def test_status_paths_match_oracle(oracle):
     fin = np.isfinite(o["x"]).all(0) & np.isfinite(o["k"]).all(0)
     ex, ek = U.ray_errors(g, o, w.omega, w.dim)
     assert ex[fin].max() < U.TOL and ek[fin].max() < U.TOL
+    # rays frozen at a non-finite state: the same state, NaN for NaN
+    for key in ("x", "k"):
+        assert np.array_equal(g[key][:, ~fin], o[key][:, ~fin], equal_nan=True), key
+    assert np.array_equal(g["t"][~fin], o["t"][~fin])
     # RK4 with a non-finite start freezes at the start with NONFINITE
     w4 = W.make("1", 64)
     w4.x0 = w4.x0.copy()
@@ -179,3 +183,41 @@ def test_plain_adjoint_matches_persistent(cfg, n, steps):
     assert np.array_equal(ax, bx) and np.array_equal(ak, bk)
     for p1, p2 in zip(ap, bp):
         assert np.abs(p1 - p2).max() <= 1e-12 * np.abs(p1).max()
+
+
+def test_step_underflow_matches_oracle(oracle):
+    """Dormand-Prince with a tolerance the first steps cannot meet and a
+    floor hmin on the step size: about half the rays end with
+    RAY_STEP_UNDERFLOW after a run of rejected attempts, the others leave
+    the box.  Statuses, accepted steps, attempts and end states as the
+    oracle's (same controller decisions; the parity rules of the
+    Dormand-Prince tests for a decision that rounding flips)."""
+    from tests.test_gpu_parity import _dopri_check
+    w = W.make("3", 2048)
+    w.rtol = w.atol = 1e-11
+    w.h0, w.hmin = 2.0, 0.05
+    print("[case] step underflow", flush=True)
+    g = U.gpu_trace(w, block=128, compact_interval=8)
+    bad, o = U.ill_conditioned(oracle, w)
+    _dopri_check(oracle, w, g, o, bad, 0.99)
+    n_uf = int((g["status"] == rgb.RAY_STEP_UNDERFLOW).sum())
+    assert 0.2 * w.n < n_uf < 0.8 * w.n, n_uf
+    assert abs(int((o["status"] == rgb.RAY_STEP_UNDERFLOW).sum()) - n_uf) <= 2
+
+
+@pytest.mark.parametrize("t_end", [3.7, 35.0])
+def test_t_end_stop_matches_oracle(oracle, t_end):
+    """Dormand-Prince with an end time: the last step is shortened to land on
+    t_end (status RAY_OK, t == t_end exactly on both sides); with the later
+    end time about half the rays leave the box first."""
+    from tests.test_gpu_parity import _dopri_check
+    w = W.make("3", 2048)
+    print(f"[case] t_end {t_end}", flush=True)
+    g = U.gpu_trace(w, block=256, compact_interval=8, t_end=t_end)
+    bad, o = U.ill_conditioned(oracle, w, t_end=t_end)
+    _dopri_check(oracle, w, g, o, bad, 0.99)
+    done = g["status"] == rgb.RAY_OK
+    assert done.sum() > 0.4 * w.n and np.all(g["t"][done] == t_end)
+    assert np.array_equal(done, o["status"] == rgb.RAY_OK)
+    if t_end > 10:
+        assert (g["status"] == rgb.RAY_EXITED_BOX).sum() > 0.3 * w.n
