@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
+    ap.add_argument("--ckpt-every", type=int, default=0,
+                    help="adjoint checkpoint interval in steps (0 = the workload's, 100)")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the single precision side measurement (RK4 forward workloads)")
     return ap.parse_args()
@@ -93,6 +95,8 @@ class Bench:
         self.full_size = not (0 < rays < w.n)
         if not self.full_size:
             w = w.subset(rays)
+        if args.ckpt_every > 0 and w.ckpt_every > 0:
+            w.ckpt_every = args.ckpt_every
         self.w = w
         self.adjoint = cfg in ("4", "5") and full_workload
         dev = self.dev = torch.device("cuda:0")

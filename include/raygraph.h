@@ -386,9 +386,28 @@ typedef struct {
     int32_t block, rays_per_lane, compact_interval; /* last configuration used */
     int32_t grid;               /* workgroups launched (persistent) */
     int32_t tuned;              /* 1 if the values came from the autotuner */
-    double last_kernel_ms;      /* not measured by the library: 0 */
+    double last_kernel_ms;      /* device time of the last rg_trace_rays or
+                                   rg_trace_rays_adjoint call, from events
+                                   recorded around its launches on its stream
+                                   (autotuning included on a call that tuned):
+                                   -1 while that work has not finished, 0 if
+                                   it was not timed (the stream was being
+                                   captured, or rg_trace_rays_noalloc) */
 } rg_launch_info;
+/* Launch configuration and device time of the last call (does not wait). */
 rg_status rg_last_launch(const rg_program *p, rg_launch_info *out);
+
+/* Per-trace solver statistics (the diagnostics the paper plots along its
+ * rays): reduces a finished trace's per-ray outputs on the GPU into 10
+ * caller-owned device counters (uint64) stats_dev:
+ *   [0..4] rays ending with each RG_RAY_* status, [5] rays with another
+ *   status value, [6] accepted steps summed over rays, [7] attempts summed
+ *   (DOPRI54; rejected attempts = [7] - [6]), [8] most accepted steps of one
+ *   ray, [9] most attempts of one ray.
+ * d is the description the trace ran with; its status_out, steps_out and
+ * (DOPRI54) attempts_out are read, NULL ones count as 0.  Enqueued on
+ * hip_stream (order it after the trace); the counters are zeroed first. */
+rg_status rg_trace_stats(rg_program *p, const rg_trace_desc *d, uint64_t *stats_dev, void *hip_stream);
 
 /* Thread-local message for the last non-OK status on this thread. */
 const char *rg_last_error(void);

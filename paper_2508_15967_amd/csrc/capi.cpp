@@ -319,7 +319,16 @@ rg_status rg_last_launch(const rg_program *p, rg_launch_info *out) {
     if (!p || !out) return fail(RG_EINVAL, "NULL argument");
     *out = p->last;
     out->struct_size = sizeof(rg_launch_info);
-    return RG_OK;
+    GUARD_BEGIN
+    return rg::last_kernel_ms(p, &out->last_kernel_ms);
+    GUARD_END
+}
+
+rg_status rg_trace_stats(rg_program *p, const rg_trace_desc *d, uint64_t *stats_dev, void *stream) {
+    if (!p || !d) return fail(RG_EINVAL, "NULL argument");
+    GUARD_BEGIN
+    return rg::trace_stats(p, *d, stats_dev, (hipStream_t)stream);
+    GUARD_END
 }
 
 }  // extern "C"

@@ -45,4 +45,6 @@ struct rg_kargs {
     long long fill_n;
     double fill_v;
     double *fill_p;
+    // per-trace statistics (rg_stats)
+    unsigned long long *stats;
 };

@@ -656,6 +656,40 @@ extern "C" __global__ void __launch_bounds__(512) rg_newton_k(rg_kargs a) {
     }
 }
 
+// ------------------------------------------------------ trace statistics --
+// Rays per termination status, accepted steps and attempts summed and their
+// largest per-ray values, over a finished trace's outputs.  Each lane
+// counts a grid-stride share of the rays, the wave sums them by shuffles,
+// and lane 0 folds the wave's totals into the counters with one atomic
+// each.  stats: [0..4] rays per status, [5] other status values, [6] steps,
+// [7] attempts, [8] most steps, [9] most attempts.
+#define RG_NSTATS 10
+extern "C" __global__ void __launch_bounds__(512) rg_stats(rg_kargs a) {
+    unsigned long long c[RG_NSTATS];
+    for (int i = 0; i < RG_NSTATS; i++) c[i] = 0;
+    const long long G = (long long)gridDim.x * blockDim.x;
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < a.n_run; r += G) {
+        const int s = a.status_out ? a.status_out[r] : 0;
+        for (int k = 0; k < 6; k++) c[k] += ((unsigned)s < 5u ? s : 5) == k;
+        const unsigned long long st = a.steps_out ? (unsigned)a.steps_out[r] : 0u;
+        const unsigned long long at = a.attempts_out ? (unsigned)a.attempts_out[r] : 0u;
+        c[6] += st;
+        c[7] += at;
+        c[8] = st > c[8] ? st : c[8];
+        c[9] = at > c[9] ? at : c[9];
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int i = 0; i < RG_NSTATS; i++) {
+            const unsigned long long o = __shfl_xor(c[i], off);
+            c[i] = i < 8 ? c[i] + o : (o > c[i] ? o : c[i]);
+        }
+    if ((threadIdx.x & 63) == 0) {
+        for (int i = 0; i < 8; i++)
+            if (c[i]) atomicAdd(a.stats + i, c[i]);
+        for (int i = 8; i < RG_NSTATS; i++) atomicMax(a.stats + i, c[i]);
+    }
+}
+
 // ----------------------------------------------------------------- utils --
 extern "C" __global__ void __launch_bounds__(512) rg_fill_f64(rg_kargs a) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -120,13 +120,19 @@ RG_FN double rg_rcp(double d) {
 
 // kNonPos: the caller guarantees x <= 0 or NaN (the emitter proves it from
 // the graph), so the upper clamp, whose only role is to keep n in range for
-// x > 1100, is left out (one instruction).
+// x > 1100, is left out, and the lower clamp is a plain maximum, which maps
+// a NaN argument to -1100 and so to e^x = 0 (one instruction against a
+// compare and two selects).  A proven non-positive argument is NaN only
+// when the stage state it is computed from is (its sums have terms of one
+// sign, so no inf - inf); the step or attempt through that state is then
+// non-finite in the state's own NaN component and is rejected, with the
+// same outcome whatever the exponential returned.
 template <bool kNonPos>
 RG_FN double rg_exp_tab(double x, const double *tab) {
-    // below -1100 the result is 0 (a select keeps NaN); above 1100 n stays
-    // bounded while r grows with x, so the result overflows to +inf, and a
-    // NaN reaches r and the result
-    x = x < -1100.0 ? -1100.0 : x;
+    // below -1100 the result is 0 (the general form's select keeps NaN);
+    // above 1100 n stays bounded while r grows with x, so the result
+    // overflows to +inf, and a NaN reaches r and the result
+    x = kNonPos ? fmax(x, -1100.0) : (x < -1100.0 ? -1100.0 : x);
     // n = x N/ln2 rounded to nearest (even) by adding 1.5 2^52, whose ulp is
     // 1: the sum holds n in its low 32 bits (two's complement), and
     // subtracting the constant again gives n as a double

@@ -57,6 +57,10 @@ struct rg_program {
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
     rg_launch_info last{};
+    // events around the last trace or adjoint call's launches (start, stop);
+    // ev_state 1: both recorded for that call
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int ev_state = 0;
 
     ~rg_program();
 };
@@ -71,6 +75,8 @@ rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s);
 rg_status adjoint(rg_program *p, const rg_adjoint_desc &d, hipStream_t s);
 rg_status workspace_size(rg_program *p, const rg_trace_desc &d, size_t *bytes);
 rg_status program_load(rg_program *p);
+rg_status last_kernel_ms(const rg_program *p, double *ms);
+rg_status trace_stats(rg_program *p, const rg_trace_desc &d, uint64_t *stats, hipStream_t s);
 rg_status trace_noalloc(rg_program *p, const rg_trace_desc &d, hipStream_t s);
 rg_status adjoint_workspace_size(rg_program *p, const rg_adjoint_desc &d, size_t *bytes);
 rg_status solve_k(rg_program *p, const rg_solve_desc &d, hipStream_t s);

@@ -36,7 +36,7 @@ static const char *const KERNELS[] = {
     "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
     "rg_dopri_persistent", "rg_dopri_plain_init", "rg_dopri_plain_step", "rg_fill_f64",
     "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k", "rg_rk4_f32",
-    "rg_adjp_init", "rg_adjp_seg", "rg_adjp_fwd", "rg_adjp_rev", "rg_adjp_finish"};
+    "rg_adjp_init", "rg_adjp_seg", "rg_adjp_fwd", "rg_adjp_rev", "rg_adjp_finish", "rg_stats"};
 
 static void drop_graphs(rg_program *p) {
     for (GraphEntry &ge : p->graphs) {
@@ -50,6 +50,8 @@ static void drop_graphs(rg_program *p) {
 
 rg_program::~rg_program() {
     rg::drop_graphs(this);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (module) (void)hipModuleUnload(module);
 }
@@ -208,6 +210,30 @@ static rg_status run_seq(rg_program *p, const std::vector<Launch> &seq, bool gra
 }
 
 static unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// Events around a call's launch sequence on the caller's stream, so that
+// rg_last_launch can report its device time once it has run.  Not recorded
+// while the stream is being captured (the events would become graph nodes)
+// or when timing is off (the no-allocation entry point).
+static void time_mark(rg_program *p, hipStream_t s, int which) {
+    if (which == 0) p->ev_state = 0;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (!p->ev[which] && hipEventCreate(&p->ev[which]) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ev[which] = nullptr;
+        return;
+    }
+    if (hipEventRecord(p->ev[which], s) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (which == 1 && p->ev_state == 0) p->ev_state = 1;
+    if (which == 0) p->ev_state = 0;
+}
 
 static rg_status occupancy_grid(rg_program *p, const char *name, int block, long long want, unsigned *grid) {
     hipFunction_t f;
@@ -652,7 +678,60 @@ static rg_status trace_impl(rg_program *p, const rg_trace_desc &d, hipStream_t s
     return RG_OK;
 }
 
-rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) { return trace_impl(p, d, s, false); }
+rg_status trace(rg_program *p, const rg_trace_desc &d, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    time_mark(p, s, 0);
+    rg_status st = trace_impl(p, d, s, false);
+    if (st == RG_OK) time_mark(p, s, 1);
+    else p->ev_state = 0;
+    return st;
+}
+
+rg_status last_kernel_ms(const rg_program *p, double *ms) {
+    *ms = 0.0;
+    if (p->ev_state != 1 || !p->ev[0] || !p->ev[1]) return RG_OK;
+    hipError_t e = hipEventQuery(p->ev[1]);
+    if (e == hipErrorNotReady) {
+        (void)hipGetLastError();
+        *ms = -1.0;
+        return RG_OK;
+    }
+    float t = 0.0f;
+    if (e != hipSuccess || hipEventElapsedTime(&t, p->ev[0], p->ev[1]) != hipSuccess) {
+        (void)hipGetLastError();
+        return RG_OK;
+    }
+    *ms = t;
+    return RG_OK;
+}
+
+rg_status trace_stats(rg_program *p, const rg_trace_desc &d, uint64_t *stats, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    if (d.struct_size < sizeof(rg_trace_desc)) return fail(RG_EINVAL, "rg_trace_desc.struct_size too small");
+    const size_t n = d.n_rays;
+    RGCHK(check_dev(stats, 8 * 10, "stats"));
+    if (d.status_out) RGCHK(check_dev(d.status_out, 4 * n, "status_out"));
+    if (d.steps_out) RGCHK(check_dev(d.steps_out, 4 * n, "steps_out"));
+    if (d.integrator == RG_DOPRI54 && d.attempts_out) RGCHK(check_dev(d.attempts_out, 4 * n, "attempts_out"));
+    rg_kargs f;
+    std::memset(&f, 0, sizeof f);
+    f.fill_p = (double *)stats;
+    f.fill_n = 10;
+    f.fill_v = 0.0;  // all-zero bits
+    RGCHK(launch_one(p, Launch{"rg_fill_f64", 1, 64, f}, s));
+    if (n == 0) return RG_OK;
+    rg_kargs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = (long long)n;
+    a.n_run = (long long)n;
+    a.status_out = d.status_out;
+    a.steps_out = d.steps_out;
+    a.attempts_out = d.integrator == RG_DOPRI54 ? d.attempts_out : nullptr;
+    a.stats = (unsigned long long *)stats;
+    unsigned grid;
+    RGCHK(occupancy_grid(p, "rg_stats", 256, (long long)cdiv(n, 256), &grid));
+    return launch_one(p, Launch{"rg_stats", grid, 256, a}, s);
+}
 
 rg_status program_load(rg_program *p) {
     RGCHK(ensure_module(p));
@@ -791,7 +870,7 @@ rg_status adjoint_workspace_size(rg_program *p, const rg_adjoint_desc &ad, size_
     return adjoint_bytes(p, *ad.fwd, bytes);
 }
 
-rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
+static rg_status adjoint_impl(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     RGCHK(ensure_module(p));
     RGCHK(adj_check(p, ad));
     const rg_trace_desc &d = *ad.fwd;
@@ -833,7 +912,7 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     rg_trace_desc fd;
     Carve cw{(char *)ad.workspace};
     carve_adjoint(p, d, pl, a, fd, cw);
-    if (pl.internal_fwd) RGCHK(trace(p, fd, s));  // checkpoints and step counts into the workspace
+    if (pl.internal_fwd) RGCHK(trace_impl(p, fd, s, false));  // checkpoints and step counts into the workspace
     const int block = pl.block;
     const unsigned grid = pl.grid;
     const int stride = pl.stride;
@@ -882,6 +961,15 @@ rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
     p->last.block = block;
     p->last.grid = (int)grid;
     return RG_OK;
+}
+
+rg_status adjoint(rg_program *p, const rg_adjoint_desc &ad, hipStream_t s) {
+    RGCHK(ensure_module(p));
+    time_mark(p, s, 0);
+    rg_status st = adjoint_impl(p, ad, s);
+    if (st == RG_OK) time_mark(p, s, 1);
+    else p->ev_state = 0;
+    return st;
 }
 
 rg_status solve_k(rg_program *p, const rg_solve_desc &d, hipStream_t s) {

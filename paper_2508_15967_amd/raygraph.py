@@ -64,7 +64,7 @@ SYMBOLS = [
     "rg_destroy_program", "rg_program_info_get", "rg_program_source", "rg_program_functions",
     "rg_trace_rays", "rg_trace_rays_adjoint", "rg_eval_rays", "rg_last_launch", "rg_last_error",
     "rg_solve_k", "rg_workspace_size", "rg_adjoint_workspace_size", "rg_program_load",
-    "rg_trace_rays_noalloc",
+    "rg_trace_rays_noalloc", "rg_trace_stats",
 ]
 
 
@@ -448,6 +448,18 @@ class Program:
         b = C.c_size_t()
         _chk(_lib.rg_adjoint_workspace_size(self.h, C.byref(a), C.byref(b)), "rg_adjoint_workspace_size")
         return int(b.value)
+
+    def trace_stats(self, d: TraceDesc, stream=None) -> Dict:
+        """Solver statistics of a finished trace (rg_trace_stats), on the host."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        st = torch.empty(10, dtype=torch.int64, device=dev)
+        _chk(_lib.rg_trace_stats(self.h, C.byref(d), C.c_void_p(_dptr(st)),
+                                 C.c_void_p(_stream_handle(stream))), "rg_trace_stats")
+        v = [int(x) for x in st.cpu().tolist()]
+        return {"by_status": {s: v[s] for s in range(5)}, "other_status": v[5], "steps": v[6],
+                "attempts": v[7], "rejected": v[7] - v[6] if v[7] else 0, "max_steps": v[8],
+                "max_attempts": v[9]}
 
     def load(self):
         """Load the code object on the current device (rg_program_load)."""

@@ -290,8 +290,9 @@ def test_exp_within_ulps():
 def test_exp_of_nonpositive_argument_within_ulps():
     """The device exponential without the overflow clamp, which the emitter
     takes where the graph proves the argument non-positive (here -x0^2):
-    within 1.5 ulp of the correctly rounded e^(-x0^2), and exact at 0, -0,
-    at underflow, at +-inf and NaN (D = omega e^(-x0^2), omega = 1)."""
+    within 1.5 ulp of the correctly rounded e^(-x0^2), exact at 0, -0, at
+    underflow and at +-inf, and 0 at a NaN argument (its lower clamp is a
+    maximum) (D = omega e^(-x0^2), omega = 1)."""
     from paper_2508_15967_amd import raygraph as rgb
     from tests.test_emit_host import _exp_reference, _exp_ulps
     torch = U.torch_mod()
@@ -301,7 +302,7 @@ def test_exp_of_nonpositive_argument_within_ulps():
     rng = np.random.default_rng(29)
     x = np.concatenate([rng.uniform(0.0, 28.0, 4000), rng.uniform(0.0, 1.0, 2000),
                         rng.uniform(-5.0, 5.0, 2000)])
-    special = np.array([0.0, -0.0, 27.3, 33.4, 40.0, 1e200, np.inf, -np.inf, np.nan])
+    special = np.array([0.0, -0.0, 27.3, 33.4, 40.0, 1e200, np.inf, -np.inf])
     xs = np.concatenate([x, special])
     y = np.zeros((4, xs.size))
     y[0] = xs
@@ -318,6 +319,10 @@ def test_exp_of_nonpositive_argument_within_ulps():
     same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
     same |= np.isfinite(ref_sp) & (ref_sp > 0) & (_exp_ulps(got_sp, ref_sp) <= 1.5)
     assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+    yn = np.zeros((4, 1))
+    yn[0], yn[2] = np.nan, 1.0
+    _, Dn = prog.eval(U.dev(yn), U.dev(np.ones(1)))
+    assert Dn.cpu().numpy()[0] == 0.0
 
 
 @pytest.mark.parametrize("cfg", ["1", "4", "5"])

@@ -221,3 +221,33 @@ def test_t_end_stop_matches_oracle(oracle, t_end):
     assert np.array_equal(done, o["status"] == rgb.RAY_OK)
     if t_end > 10:
         assert (g["status"] == rgb.RAY_EXITED_BOX).sum() > 0.3 * w.n
+
+
+def test_trace_stats_and_kernel_time():
+    """rg_trace_stats reduces a finished trace's statuses, steps and attempts
+    on the GPU: the same counts, sums and maxima as numpy over the outputs;
+    rg_last_launch reports the last call's device time once it has run."""
+    torch = U.torch_mod()
+    w = W.make("3", 6000)
+    _, _, prog, _ = U.program(w)
+    g = U.gpu_trace(w, block=128, compact_interval=8)
+    desc = g["_t"]["_desc"]
+    torch.cuda.synchronize()
+    ms = prog.last_launch()["last_kernel_ms"]
+    assert ms > 0.0, ms
+    st = prog.trace_stats(desc)
+    for s in range(5):
+        assert st["by_status"][s] == int((g["status"] == s).sum()), s
+    assert st["other_status"] == 0
+    assert st["steps"] == int(g["steps"].astype(np.int64).sum())
+    assert st["attempts"] == int(g["attempts"].astype(np.int64).sum())
+    assert st["rejected"] == st["attempts"] - st["steps"] > 0
+    assert st["max_steps"] == int(g["steps"].max()) and st["max_attempts"] == int(g["attempts"].max())
+    # fixed-step RK4: steps only, attempts 0
+    w2 = W.make("2", 3000)
+    w2.n_steps = 200
+    g2 = U.gpu_trace(w2, block=256, rays_per_lane=1)
+    _, _, prog2, _ = U.program(w2)
+    st2 = prog2.trace_stats(g2["_t"]["_desc"])
+    assert st2["by_status"][0] == 3000 and st2["steps"] == 3000 * 200 and st2["attempts"] == 0
+    assert st2["max_steps"] == 200
