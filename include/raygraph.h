@@ -161,6 +161,16 @@ typedef struct {
     int32_t fp32;           /* 1: also emit a single precision right-hand side and
                                build the RG_FP32 persistent RK4 kernel (graphs
                                without spline nodes; RG_EUNSUPPORTED otherwise) */
+    int32_t deterministic;  /* 1: the adjoint sums spline-coefficient gradients in
+                               a fixed order, so that they are bitwise the same
+                               from run to run for a given launch configuration
+                               (each wave accumulates into its own copy of the
+                               table in the workspace, the copies summed in wave
+                               order; slower and more workspace).  Without it
+                               those sums go through shared LDS atomics whose
+                               order varies at the rounding level.  Scalar
+                               parameter gradients are summed in a fixed order
+                               either way. */
 } rg_compile_opts;
 
 /* Differentiate D (eqs. 2-3), reduce and CSE, emit the HIP right-hand side
@@ -239,7 +249,8 @@ typedef struct {
     int32_t mode;               /* RG_PERSISTENT | RG_PLAIN (one launch per step) */
     int32_t use_hipgraph;       /* replay the launch sequence from a captured hipGraph */
     int32_t block;              /* threads per workgroup, 0 = tuned */
-    int32_t rays_per_lane;      /* 1 | 2, 0 = tuned */
+    int32_t rays_per_lane;      /* 1 | 2 | 4 (4: right-hand sides under 200 issued
+                                   flops), 0 = tuned */
     int32_t compact_interval;   /* DOPRI54: refill dead lanes every this many attempts,
                                    0 = tuned, -1 = only when a whole wave is dead */
     int32_t *attempts_out;      /* DOPRI54: [n] step attempts incl. rejected ones, nullable */
@@ -255,6 +266,11 @@ typedef struct {
        entry do not matter; the call's stream work owns it until it ends. */
     void *workspace;
     size_t workspace_bytes;
+    int32_t min_waves_per_simd; /* persistent FP64 RK4, one ray per lane: 4 = the
+                                   kernel variant built for at least 4 waves per
+                                   SIMD (at most 128 VGPRs; same results);
+                                   0 = the autotuner's choice when it tunes,
+                                   else the plain kernel */
 } rg_trace_desc;
 
 /* Trace n_rays rays.  RK4 runs exactly n_steps steps per ray (fewer if it
@@ -386,6 +402,7 @@ typedef struct {
     int32_t block, rays_per_lane, compact_interval; /* last configuration used */
     int32_t grid;               /* workgroups launched (persistent) */
     int32_t tuned;              /* 1 if the values came from the autotuner */
+    int32_t min_waves_per_simd; /* 4 if the at-least-four-waves RK4 variant ran */
     double last_kernel_ms;      /* device time of the last rg_trace_rays or
                                    rg_trace_rays_adjoint call, from events
                                    recorded around its launches on its stream

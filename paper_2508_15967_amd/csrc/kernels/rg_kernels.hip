@@ -31,19 +31,33 @@ __shared__ double rg_spl_lds[RG_SPL_TOTAL];
 
 // Gradient accumulator for spline coefficient tables (adjoint only): the
 // 16 coefficient gradients of the current cell stay in registers while the
-// ray stays in that cell and are flushed to an LDS copy of the table with
-// atomics when it leaves.
+// ray stays in that cell and are flushed with atomics when it leaves: to an
+// LDS copy of the table shared by the workgroup, or, with
+// RG_DET_GRAD (deterministic sums), to the wave's own copy in its slot of
+// the per-wave partials (global memory), so that each copy is added to by
+// one wave in program order and the partials are then summed in a fixed
+// order.
 #if RG_HAS_VJP && RG_NSPLTAB > 0
+#if !RG_DET_GRAD
 __shared__ double rg_spl_grad_lds[RG_SPL_TOTAL];
+#endif
 struct rg_GA {
     int cx[RG_NSPLTAB], cy[RG_NSPLTAB];
     double acc[RG_NSPLTAB][16];
-    __device__ __forceinline__ void init() {
+    double *tab;  // the table copy this lane's flushes go to
+    // part: this wave's slot of the partials ([RG_NGRAD scalars][tables])
+    __device__ __forceinline__ void init(double *part) {
         for (int k = 0; k < RG_NSPLTAB; k++) { cx[k] = -1; cy[k] = -1; }
+#if RG_DET_GRAD
+        tab = part + RG_NGRAD;
+#else
+        (void)part;
+        tab = rg_spl_grad_lds;
+#endif
     }
     __device__ __forceinline__ void flush(int k) {
         if (cx[k] >= 0) {
-            double *base = rg_spl_grad_lds + rg_spl_off[k] + (cx[k] - 1) * rg_spl_ny[k] + (cy[k] - 1);
+            double *base = tab + rg_spl_off[k] + (cx[k] - 1) * rg_spl_ny[k] + (cy[k] - 1);
             for (int a = 0; a < 4; a++)
                 for (int b = 0; b < 4; b++) atomicAdd(base + a * rg_spl_ny[k] + b, acc[k][4 * a + b]);
         }
@@ -61,7 +75,7 @@ struct rg_GA {
 };
 #else
 struct rg_GA {
-    __device__ __forceinline__ void init() {}
+    __device__ __forceinline__ void init(double *) {}
     __device__ __forceinline__ void flush(int) {}
     __device__ __forceinline__ void add(int, int, int, const double *) {}
 };
@@ -273,6 +287,15 @@ __device__ __forceinline__ void rg_rk4_persistent(const rg_kargs &a) {
 
 extern "C" __global__ void __launch_bounds__(512) rg_rk4_r1(rg_kargs a) { rg_rk4_persistent<double, 1>(a); }
 extern "C" __global__ void __launch_bounds__(512) rg_rk4_r2(rg_kargs a) { rg_rk4_persistent<double, 2>(a); }
+// The same one-ray-per-lane kernel built for at least four waves per SIMD
+// (at most 128 VGPRs): where the natural register count is a little above
+// that, the extra wave can hide more latency than the spills cost; the
+// autotuner takes it only where it measures faster.  Same arithmetic.
+extern "C" __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+rg_rk4_r1o4(rg_kargs a) { rg_rk4_persistent<double, 1>(a); }
+#if RG_HAS_R4
+extern "C" __global__ void __launch_bounds__(512) rg_rk4_r4(rg_kargs a) { rg_rk4_persistent<double, 4>(a); }
+#endif
 #if RG_HAS_F32
 extern "C" __global__ void __launch_bounds__(512) rg_rk4_f32(rg_kargs a) { rg_rk4_persistent<float, 1>(a); }
 #endif
@@ -819,6 +842,18 @@ __device__ __forceinline__ void rg_adjoint_step(const double *sp, long long SL, 
 // in a fixed order (wave shuffles, then waves in order), the spline
 // coefficients from the LDS accumulator; written (add = false) or added to
 // what the workgroup's earlier launches left (add = true).
+// The partials' slot of this workgroup (one per workgroup), or of this
+// wave (RG_DET_GRAD: one per wave, the workgroup's scalar sums in the slot
+// of its first wave).
+__device__ __forceinline__ double *rg_part_slot(const rg_kargs &a) {
+    if (!a.gpart) return nullptr;
+#if RG_DET_GRAD
+    return a.gpart + ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * a.part_stride;
+#else
+    return a.gpart + (long long)blockIdx.x * a.part_stride;
+#endif
+}
+
 template <typename GPT>
 __device__ __forceinline__ void rg_write_partials(const rg_kargs &a, GPT gp, rg_GA &G, bool add) {
 #if RG_NSPLTAB > 0
@@ -833,13 +868,19 @@ __device__ __forceinline__ void rg_write_partials(const rg_kargs &a, GPT gp, rg_
         if (lane == 0) rg_red_lds[wave * RG_NGRAD1 + s] = v;
     }
     __syncthreads();
+#if RG_DET_GRAD
+    // scalar sums into the first wave's slot; the spline tables are already
+    // in each wave's slot
+    double *out = a.gpart + (long long)blockIdx.x * nw * a.part_stride;
+#else
     double *out = a.gpart + (long long)blockIdx.x * a.part_stride;
+#endif
     for (int s = threadIdx.x; s < RG_NGRAD; s += blockDim.x) {
         double v = 0.0;
         for (int w = 0; w < nw; w++) v += rg_red_lds[w * RG_NGRAD1 + s];
         out[s] = add ? out[s] + v : v;
     }
-#if RG_NSPLTAB > 0
+#if RG_NSPLTAB > 0 && !RG_DET_GRAD
     for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x)
         out[RG_NGRAD + i] = add ? out[RG_NGRAD + i] + rg_spl_grad_lds[i] : rg_spl_grad_lds[i];
 #endif
@@ -853,13 +894,13 @@ __shared__ double rg_gp_lds[RG_NGRAD1 * RG_ADJ_BLOCK];
 #endif
 extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) RG_ADJ_OCCUPANCY rg_rk4_adjoint(rg_kargs a) {
     rg_stage_tables(a);
-#if RG_NSPLTAB > 0
+#if RG_NSPLTAB > 0 && !RG_DET_GRAD
     for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) rg_spl_grad_lds[i] = 0.0;
     __syncthreads();
 #endif
     const rg_P P = rg_params(a);
     rg_GA G;
-    G.init();
+    G.init(rg_part_slot(a));  // (RG_DET_GRAD: the slots were zeroed before the launch)
 #if RG_GP_LDS
     for (int i = 0; i < RG_NGRAD1; i++) rg_gp_lds[i * RG_ADJ_BLOCK + threadIdx.x] = 0.0;
     const rg_GPLds gp{rg_gp_lds + threadIdx.x};
@@ -920,9 +961,14 @@ extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) RG_ADJ_OCCUPANCY rg_r
 // gradient partials to its own slot.  Rays stopped before a step skip it.
 extern "C" __global__ void __launch_bounds__(512) rg_adjp_init(rg_kargs a) {
     const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a.gpart)  // this workgroup's slot (same grid as rg_adjp_rev)
-        for (int s = threadIdx.x; s < a.part_stride; s += blockDim.x)
-            a.gpart[(long long)blockIdx.x * a.part_stride + s] = 0.0;
+    if (a.gpart) {  // this workgroup's slot, or its waves' slots (same grid as rg_adjp_rev)
+#if RG_DET_GRAD
+        const long long m = (long long)(blockDim.x >> 6) * a.part_stride;
+#else
+        const long long m = a.part_stride;
+#endif
+        for (long long s = threadIdx.x; s < m; s += blockDim.x) a.gpart[(long long)blockIdx.x * m + s] = 0.0;
+    }
     if (r >= a.n_run) return;
     for (int i = 0; i < RG_DIM; i++) {
         a.s_lam[i * n + r] = a.lam_x[i * n + r];
@@ -956,13 +1002,13 @@ extern "C" __global__ void __launch_bounds__(512) rg_adjp_fwd(rg_kargs a) {
 
 extern "C" __global__ void __launch_bounds__(RG_ADJ_BLOCK) rg_adjp_rev(rg_kargs a) {
     rg_stage_tables(a);
-#if RG_NSPLTAB > 0
+#if RG_NSPLTAB > 0 && !RG_DET_GRAD
     for (int i = threadIdx.x; i < RG_SPL_TOTAL; i += blockDim.x) rg_spl_grad_lds[i] = 0.0;
     __syncthreads();
 #endif
     const rg_P P = rg_params(a);
     rg_GA G;
-    G.init();
+    G.init(rg_part_slot(a));
     double gp[RG_NGRAD1];
     for (int i = 0; i < RG_NGRAD1; i++) gp[i] = 0.0;
     const long long n = a.n, r = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -304,6 +304,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     // hundred issued flops against a global-memory latency the few waves of
     // a small ray batch cannot hide); otherwise they are stored.
     p->adj_recompute = fl_rhs.issued + fl_rhs.inv_issued < 400.0;
+    // Four rays per lane only for cheap right-hand sides (four copies of the
+    // state and stages must stay in registers).
+    p->has_r4 = !p->rolled && fl_rhs.issued < 200.0;
     // With stored stage states the reverse step is a loop around one large
     // VJP whose registers decide the waves per SIMD: there the per-lane
     // gradient partials of scalar parameters are accumulated in LDS instead
@@ -315,6 +318,11 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         const size_t lds = ngrad1 * kAdjointBlock * 8 + (size_t)p->spl_total * 16 + 2048 + 8 * ngrad1 * 8;
         p->gp_lds = p->has_vjp && !p->adj_recompute && lds <= 53248;
     }
+    // deterministic spline-coefficient gradients: asked for, and there are
+    // spline tables whose gradients would otherwise go through shared atomics
+    p->det_grad = opts.deterministic && p->has_vjp && p->spl_total > 0;
+    {
+    }
 
     // ---- configuration header
     std::ostringstream cs;
@@ -322,10 +330,12 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
        << p->n_params << "\n#define RG_NGRAD " << p->grad_param.size() << "\n#define RG_NSPLTAB "
        << p->spl_param.size() << "\n#define RG_SPL_TOTAL " << (p->spl_total ? p->spl_total : 1)
        << "\n#define RG_HAS_VJP " << (p->has_vjp ? 1 : 0) << "\n#define RG_HAS_F32 " << (p->has_f32 ? 1 : 0)
+       << "\n#define RG_HAS_R4 " << (p->has_r4 ? 1 : 0)
        << "\n#define RG_USES_EXP " << (p->functions_src.find("rg_exp") != std::string::npos ? 1 : 0)
        << "\n#define RG_RHS_ZERO " << zero_mask
        << "u\n#define RG_ROLL " << (p->rolled ? 1 : 0) << "\n#define RG_ADJ_RECOMPUTE "
        << (p->adj_recompute ? 1 : 0) << "\n#define RG_GP_LDS " << (p->gp_lds ? 1 : 0)
+       << "\n#define RG_DET_GRAD " << (p->det_grad ? 1 : 0)
        << "\n#define RG_ADJ_BLOCK " << kAdjointBlock << "\n";
     cs << int_array("rg_spl_param", p->spl_param) << int_array("rg_spl_off", p->spl_off)
        << int_array("rg_spl_len", p->spl_len) << int_array("rg_spl_ny", p->spl_ny)

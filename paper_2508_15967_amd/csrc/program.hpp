@@ -21,6 +21,7 @@ constexpr int kAdjointBlock = 256;
 
 struct TuneEntry {
     int block = 256, rpl = 1, compact = 64;
+    int occ = 0;  // 1: the RK4 kernel variant built for at least 4 waves per SIMD
 };
 
 struct GraphEntry {
@@ -37,8 +38,10 @@ struct rg_program {
     bool compile_only = false;
     bool rolled = false;  // RK4 stage loops rolled (RG_ROLL)
     bool has_f32 = false; // single precision RK4 kernel built (RG_HAS_F32)
+    bool has_r4 = false;  // four-rays-per-lane RK4 kernel built (RG_HAS_R4)
     bool adj_recompute = false;  // adjoint recomputes stage states (RG_ADJ_RECOMPUTE)
     bool gp_lds = false;  // adjoint gradient partials in LDS, 3 waves per SIMD (RG_GP_LDS)
+    bool det_grad = false; // spline-coefficient gradients summed in a fixed order (RG_DET_GRAD)
     // gradient layout
     std::vector<int> grad_param, grad_elem;       // scalar slots
     std::vector<int> spl_param, spl_off, spl_len, spl_ny;

@@ -33,7 +33,7 @@ namespace rg {
     } while (0)
 
 static const char *const KERNELS[] = {
-    "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
+    "rg_rk4_r1", "rg_rk4_r2", "rg_rk4_r1o4", "rg_rk4_r4", "rg_rk4_plain_init", "rg_rk4_plain_step", "rg_plain_finish",
     "rg_dopri_persistent", "rg_dopri_plain_init", "rg_dopri_plain_step", "rg_fill_f64",
     "rg_eval_points", "rg_rk4_adjoint", "rg_grad_finalize", "rg_newton_k", "rg_rk4_f32",
     "rg_adjp_init", "rg_adjp_seg", "rg_adjp_fwd", "rg_adjp_rev", "rg_adjp_finish", "rg_stats"};
@@ -260,7 +260,15 @@ static rg_status validate(rg_program *p, const rg_trace_desc &d, rg_kargs &a, bo
     if (d.mode != RG_PERSISTENT && d.mode != RG_PLAIN) return fail(RG_EINVAL, "unknown mode");
     if (d.block != 0 && d.block != 64 && d.block != 128 && d.block != 256 && d.block != 512)
         return fail(RG_EINVAL, "block must be 0, 64, 128, 256 or 512");
-    if (d.rays_per_lane < 0 || d.rays_per_lane > 2) return fail(RG_EINVAL, "rays_per_lane must be 0, 1 or 2");
+    if (d.rays_per_lane < 0 || d.rays_per_lane > 4 || d.rays_per_lane == 3)
+        return fail(RG_EINVAL, "rays_per_lane must be 0, 1, 2 or 4");
+    if (d.rays_per_lane == 4 && !p->has_r4)
+        return fail(RG_EUNSUPPORTED, "four rays per lane are built only for right-hand sides under 200 issued flops");
+    if (d.min_waves_per_simd != 0 && d.min_waves_per_simd != 4)
+        return fail(RG_EINVAL, "min_waves_per_simd must be 0 or 4");
+    if (d.min_waves_per_simd == 4 && (d.integrator != RG_RK4 || d.mode != RG_PERSISTENT || d.rays_per_lane > 1 ||
+                                      d.precision != RG_FP64))
+        return fail(RG_EUNSUPPORTED, "min_waves_per_simd = 4 is built for persistent FP64 RK4, one ray per lane");
     if (d.precision != RG_FP64 && d.precision != RG_FP32) return fail(RG_EINVAL, "unknown precision");
     if (d.precision == RG_FP32) {
         if (!p->has_f32) return fail(RG_ESTATE, "RG_FP32 needs a program compiled with fp32 = 1");
@@ -371,14 +379,14 @@ static void tune_load(rg_program *p) {
     std::ifstream in(f);
     std::string key;
     TuneEntry t;
-    while (in >> key >> t.block >> t.rpl >> t.compact) p->tune[key] = t;
+    while (in >> key >> t.block >> t.rpl >> t.compact >> t.occ) p->tune[key] = t;
 }
 
 static void tune_save(const std::string &key, const TuneEntry &t) {
     std::string f = tune_file();
     if (f.empty()) return;
     std::ofstream out(f, std::ios::app);
-    out << key << " " << t.block << " " << t.rpl << " " << t.compact << "\n";
+    out << key << " " << t.block << " " << t.rpl << " " << t.compact << " " << t.occ << "\n";
 }
 
 // Fastest of three timed runs after a warm-up run.
@@ -402,20 +410,32 @@ static rg_status time_seq(rg_program *p, const std::vector<Launch> &seq, hipStre
     return RG_OK;
 }
 
+// Keyed by program, integrator, ray count (power of two below it), the
+// device's architecture name and CU count, and the hipRTC version.
 static std::string tune_key(rg_program *p, const char *what, long long n) {
     int lg = 0;
     while ((1ll << (lg + 1)) <= n) lg++;
     int rtc_major = 0, rtc_minor = 0;
     hiprtcVersion(&rtc_major, &rtc_minor);
-    char buf[192];
-    std::snprintf(buf, sizeof buf, "%016llx|%s|n2^%d|cu%d|gfx950|hiprtc%d.%d", (unsigned long long)p->hash, what,
-                  lg, p->n_cu, rtc_major, rtc_minor);
+    std::string arch = "unknown";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');  // drop feature suffixes (":sramecc+:xnack-")
+        if (colon != std::string::npos) arch.resize(colon);
+    } else {
+        (void)hipGetLastError();
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%016llx|%s|n2^%d|cu%d|%s|hiprtc%d.%d", (unsigned long long)p->hash, what,
+                  lg, p->n_cu, arch.c_str(), rtc_major, rtc_minor);
     return buf;
 }
 
 static rg_status persistent_rk4_seq(rg_program *p, const rg_kargs &a, int block, int rpl,
-                                    std::vector<Launch> &seq, bool fp32 = false) {
-    const char *name = fp32 ? "rg_rk4_f32" : rpl == 2 ? "rg_rk4_r2" : "rg_rk4_r1";
+                                    std::vector<Launch> &seq, bool fp32 = false, int occ = 0) {
+    const char *name = fp32 ? "rg_rk4_f32" : rpl == 4 ? "rg_rk4_r4" : rpl == 2 ? "rg_rk4_r2"
+                                                     : occ ? "rg_rk4_r1o4" : "rg_rk4_r1";
     unsigned grid;
     RGCHK(occupancy_grid(p, name, block, (long long)cdiv(a.n_run, (long long)block * rpl), &grid));
     seq.push_back(Launch{name, grid, (unsigned)block, a});
@@ -452,13 +472,18 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     // configurations do not flip from one process to the next.
     rg_kargs t = a;
     t.n_steps = std::min(a.n_steps, std::max(128, std::min(1024, a.n_steps / 16)));
-    const std::pair<int, int> cand[] = {{1, 256}, {1, 512}, {1, 128}, {2, 256}, {2, 128}, {1, 64}, {2, 512}, {2, 64}};
+    // (rays per lane, block, at-least-four-waves variant); the variant last,
+    // so that it is taken only where it is more than 3 % faster
+    struct Cand { int rpl, block, occ; };
+    const Cand cand[] = {{1, 256, 0}, {1, 512, 0}, {1, 128, 0}, {2, 256, 0}, {2, 128, 0}, {1, 64, 0},
+                         {2, 512, 0}, {2, 64, 0}, {4, 128, 0}, {4, 256, 0}, {1, 256, 1}, {1, 512, 1}};
     std::vector<float> ms_of;
-    for (const auto &c : cand) {
+    for (const Cand &c : cand) {
         float ms = 1e30f;
-        if (!(fp32 && c.first > 1)) {
+        const bool ok = !(fp32 && (c.rpl > 1 || c.occ)) && !(c.rpl == 4 && !p->has_r4);
+        if (ok) {
             std::vector<Launch> seq;
-            RGCHK(persistent_rk4_seq(p, t, c.second, c.first, seq, fp32));
+            RGCHK(persistent_rk4_seq(p, t, c.block, c.rpl, seq, fp32, c.occ));
             RGCHK(time_seq(p, seq, s, &ms));
         }
         ms_of.push_back(ms);
@@ -467,8 +492,9 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     TuneEntry bt;
     for (size_t i = 0; i < ms_of.size(); i++)
         if (ms_of[i] <= 1.03f * best) {
-            bt.rpl = cand[i].first;
-            bt.block = cand[i].second;
+            bt.rpl = cand[i].rpl;
+            bt.block = cand[i].block;
+            bt.occ = cand[i].occ;
             break;
         }
     p->tune[key] = bt;
@@ -601,12 +627,16 @@ static rg_status trace_impl(rg_program *p, const rg_trace_desc &d, hipStream_t s
         const bool fp32 = d.precision == RG_FP32;
         TuneEntry te;
         if (d.block == 0 || (d.rays_per_lane == 0 && !fp32)) RGCHK(tune_rk4(p, a, s, &te, fp32));
+        const bool tuned = d.block == 0 || (d.rays_per_lane == 0 && !fp32);
         int block = d.block ? d.block : te.block;
         int rpl = fp32 ? 1 : d.rays_per_lane ? d.rays_per_lane : te.rpl;
+        // the at-least-four-waves variant: chosen by the tuner, or asked for
+        const int occ = rpl == 1 && !fp32 && (d.min_waves_per_simd == 4 || (tuned && d.min_waves_per_simd == 0 && te.occ));
         std::vector<Launch> seq;
-        RGCHK(persistent_rk4_seq(p, a, block, rpl, seq, fp32));
+        RGCHK(persistent_rk4_seq(p, a, block, rpl, seq, fp32, occ));
         p->last.block = block;
         p->last.rays_per_lane = rpl;
+        p->last.min_waves_per_simd = occ ? 4 : 0;
         return run_seq(p, seq, graph, s);
     }
     if (d.integrator == RG_RK4) {  // plain: one launch per step
@@ -781,6 +811,7 @@ struct AdjPlan {
     long long lanes = 0;        // per-lane segment buffer rows (persistent) or n (plain)
     int stride = 0;             // gradient slots per workgroup partial
     int ns_kept = 0;            // stage states per step in the segment buffer
+    long long n_part = 0;       // partial slots: workgroups, or waves (deterministic sums)
 };
 
 static rg_status adj_plan(rg_program *p, const rg_trace_desc &d, AdjPlan *pl) {
@@ -796,6 +827,8 @@ static rg_status adj_plan(rg_program *p, const rg_trace_desc &d, AdjPlan *pl) {
         RGCHK(occupancy_grid(p, "rg_rk4_adjoint", pl->block, (long long)cdiv(n, pl->block), &pl->grid));
         pl->lanes = (long long)pl->grid * pl->block;
     }
+    // one partials slot per workgroup, or per wave for deterministic sums
+    pl->n_part = p->det_grad ? (long long)pl->grid * ((pl->block + 63) / 64) : pl->grid;
     return RG_OK;
 }
 
@@ -831,8 +864,8 @@ static void carve_adjoint(rg_program *p, const rg_trace_desc &d, const AdjPlan &
         a.s_lam = c.take<double>(ny * n);
         a.s_t = c.take<double>(n);
     }
-    a.gpart = pl.stride > 0 ? c.take<double>((size_t)pl.grid * pl.stride) : nullptr;
-    a.n_part = (int)pl.grid;
+    a.gpart = pl.stride > 0 ? c.take<double>((size_t)pl.n_part * pl.stride) : nullptr;
+    a.n_part = (int)pl.n_part;
     a.part_stride = pl.stride;
 }
 
@@ -956,6 +989,14 @@ static rg_status adjoint_impl(rg_program *p, const rg_adjoint_desc &ad, hipStrea
         return RG_OK;
     }
 
+    if (p->det_grad && a.gpart) {  // the per-wave tables are added to from zero
+        rg_kargs f;
+        std::memset(&f, 0, sizeof f);
+        f.fill_p = a.gpart;
+        f.fill_n = (long long)pl.n_part * stride;
+        f.fill_v = 0.0;
+        RGCHK(launch_one(p, Launch{"rg_fill_f64", cdiv(f.fill_n, 256), 256, f}, s));
+    }
     RGCHK(launch_one(p, Launch{"rg_rk4_adjoint", grid, (unsigned)block, a}, s));
     if (stride > 0) RGCHK(launch_one(p, Launch{"rg_grad_finalize", cdiv(stride, 256), 256, a}, s));
     p->last.block = block;

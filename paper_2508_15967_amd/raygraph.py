@@ -78,7 +78,7 @@ class RayGraphError(RuntimeError):
 class _CompileOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("want_adjoint", C.c_int32),
                 ("compile_only", C.c_int32), ("opt_level", C.c_int32), ("arch", C.c_char_p),
-                ("fp32", C.c_int32)]
+                ("fp32", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class _ProgramInfo(C.Structure):
@@ -114,7 +114,8 @@ class TraceDesc(C.Structure):
                 ("mode", C.c_int32), ("use_hipgraph", C.c_int32), ("block", C.c_int32),
                 ("rays_per_lane", C.c_int32), ("compact_interval", C.c_int32),
                 ("attempts_out", C.c_void_p), ("precision", C.c_int32),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("min_waves_per_simd", C.c_int32)]
 
 
 class AdjointDesc(C.Structure):
@@ -134,7 +135,7 @@ class SolveDesc(C.Structure):
 class LaunchInfo(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("block", C.c_int32), ("rays_per_lane", C.c_int32),
                 ("compact_interval", C.c_int32), ("grid", C.c_int32), ("tuned", C.c_int32),
-                ("last_kernel_ms", C.c_double)]
+                ("min_waves_per_simd", C.c_int32), ("last_kernel_ms", C.c_double)]
 
 
 _lib.rg_last_error.restype = C.c_char_p
@@ -315,9 +316,9 @@ class Graph:
         return buf.value.decode()
 
     def compile(self, D: Node, want_adjoint: bool = False, compile_only: bool = False,
-                opt_level: int = 0, fp32: bool = False) -> "Program":
+                opt_level: int = 0, fp32: bool = False, deterministic: bool = False) -> "Program":
         o = _CompileOpts(C.sizeof(_CompileOpts), int(want_adjoint), int(compile_only), opt_level, None,
-                         int(fp32))
+                         int(fp32), int(deterministic))
         h = C.c_void_p()
         _chk(_lib.rg_compile(self.h, D.id, C.byref(o), C.byref(h)), "rg_compile")
         return Program(h, self.dim, list(self.param_lens), list(self.param_names))
@@ -391,7 +392,7 @@ class Program:
                   t_out=None, status_out=None, steps_out=None, checkpoint_every=0,
                   checkpoints=None, mode=PERSISTENT, use_hipgraph=False, block=0,
                   rays_per_lane=0, compact_interval=0, attempts_out=None, precision=FP64,
-                  workspace=None):
+                  workspace=None, min_waves_per_simd=0):
         import torch
         f64, i32 = torch.float64, torch.int32
         for t, nm, dt_ in ((x0, "x0", f64), (k0, "k0", f64), (omega, "omega", f64), (t0, "t0", f64),
@@ -427,6 +428,7 @@ class Program:
         d.block, d.rays_per_lane, d.compact_interval = int(block), int(rays_per_lane), int(compact_interval)
         d.attempts_out = _dptr(attempts_out)
         d.precision = int(precision)
+        d.min_waves_per_simd = int(min_waves_per_simd)
         # per-call scratch: a torch allocation of the size the library asks for
         if d.n_rays > 0:
             need = self.workspace_size(d)

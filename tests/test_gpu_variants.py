@@ -24,9 +24,13 @@ def test_rk4_variants_bitwise():
     w.n_steps = 400
     base = U.gpu_trace(w, block=256, rays_per_lane=1, store=True)
     for block in (64, 128, 512):
-        for rpl in (1, 2):
+        for rpl in (1, 2, 4):
             print(f"[case] rk4 block={block} rpl={rpl}", flush=True)
             _same(base, U.gpu_trace(w, block=block, rays_per_lane=rpl, store=True), ("x", "k", "t", "traj"))
+    for block in (256, 512):  # the kernel variant built for at least four waves per SIMD
+        print(f"[case] rk4 block={block} min_waves_per_simd=4", flush=True)
+        _same(base, U.gpu_trace(w, block=block, rays_per_lane=1, min_waves_per_simd=4, store=True),
+              ("x", "k", "t", "traj"))
     pl = U.gpu_trace(w, mode=rgb.PLAIN, block=128, store=True)
     _same(base, pl, ("x", "k", "t", "status", "steps", "traj"))
     gr = U.gpu_trace(w, block=256, rays_per_lane=2, use_hipgraph=True, store=True)
@@ -41,6 +45,13 @@ def test_rk4_autotuned_matches_fixed():
     a = U.gpu_trace(w)
     b = U.gpu_trace(w, block=64, rays_per_lane=1)
     _same(a, b)
+    # the anisotropic medium's forward (natural register count above 128:
+    # the four-wave variant differs in code, not in results)
+    w5 = W.make("5", 3000)
+    w5.n_steps = 200
+    a5 = U.gpu_trace(w5, block=256, rays_per_lane=1)
+    _same(a5, U.gpu_trace(w5, block=256, rays_per_lane=1, min_waves_per_simd=4))
+    _same(a5, U.gpu_trace(w5))
 
 
 def test_split_and_resume_bitwise():
