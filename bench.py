@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--block", type=int, default=0, help="fix the block size (0 = autotuned)")
     ap.add_argument("--rpl", type=int, default=0, help="fix rays per lane (0 = autotuned)")
     ap.add_argument("--compact", type=int, default=0, help="fix the compaction interval (0 = autotuned)")
+    ap.add_argument("--min-waves", type=int, default=0,
+                    help="4: the RK4 kernel variant built for at least four waves per SIMD (0 = autotuned)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
@@ -145,7 +147,7 @@ class Bench:
             kw["checkpoints"] = self.ckpt
         self.kw, self.outs = kw, outs
         self.stream = torch.cuda.current_stream()
-        self.desc = self.make(0, args.block, args.rpl, args.compact)
+        self.desc = self.make(0, args.block, args.rpl, args.compact, args.min_waves)
         if self.adjoint:
             self.adj = {"lx": torch.empty((d, n), dtype=torch.float64, device=dev),
                         "gx0": torch.empty((d, n), dtype=torch.float64, device=dev),
@@ -153,10 +155,10 @@ class Bench:
                         "gp": [torch.empty_like(p) for p in self.pt],
                         "tx": torch.from_numpy(w.targets).to(dev)}
 
-    def make(self, mode, block=0, rpl=0, compact=0):
+    def make(self, mode, block=0, rpl=0, compact=0, min_waves=0):
         return self.prog.make_desc(self.x0, self.k0, self.om, self.pt, mode=mode, use_hipgraph=True,
                                    block=block, rays_per_lane=rpl, compact_interval=compact,
-                                   **self.kw, **self.outs)
+                                   min_waves_per_simd=min_waves, **self.kw, **self.outs)
 
     def fwd(self, desc=None):
         self.prog.trace_desc(desc or self.desc, self.stream)
@@ -265,6 +267,8 @@ class Bench:
 
     def fwd_kernel(self):
         if self.w.integrator == self.W.RK4:
+            if self.launch.get("min_waves_per_simd") == 4:
+                return "rg_rk4_r1o4"
             return "rg_rk4_r%d" % self.launch["rays_per_lane"]
         return "rg_dopri_persistent"
 

@@ -36,7 +36,7 @@ def test_counter_summaries_are_well_formed():
     HBM total is the sum of the read and write bytes."""
     names = {W.make(c, 1).name for c in ("1", "2", "3", "4", "5", "cp")}
     names |= {W.coldplasma("O").name, W.coldplasma("X").name}
-    kernels = {"rg_rk4_r1", "rg_rk4_r2", "rg_rk4_adjoint", "rg_dopri_persistent"}
+    kernels = {"rg_rk4_r1", "rg_rk4_r2", "rg_rk4_r4", "rg_rk4_r1o4", "rg_rk4_adjoint", "rg_dopri_persistent"}
     traffic, fp64 = _entries("traffic_*.txt"), _entries("fp64_*.txt")
     assert traffic and fp64
     for fname, kv in traffic + fp64:
