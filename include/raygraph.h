@@ -303,7 +303,7 @@ rg_status rg_program_load(rg_program *p);
  *   - rg_program_load must have run on the current device (RG_ESTATE);
  *   - a trace needing more scratch than the array holds is RG_EINVAL
  *     (rg_workspace_size tells: persistent RK4 needs none, persistent
- *     Dormand-Prince 8 bytes, the plain forms 16 (RK4) or 144
+ *     Dormand-Prince 8 bytes, the plain forms 16 (RK4) or 132
  *     (Dormand-Prince, 3-D) bytes per ray);
  *   - launch parameters must be given (block; rays_per_lane for RK4;
  *     compact_interval for Dormand-Prince): no autotuning (RG_EINVAL);

@@ -5,7 +5,7 @@
 
 // Size of the static scratch array per device: the Dormand-Prince refill
 // queue, or the per-ray state of the one-launch-per-step forms for up to
-// about 260,000 rays (RK4) or 29,000 rays (Dormand-Prince).
+// about 260,000 rays (RK4) or 31,000 rays (Dormand-Prince, 3-D).
 #define RG_NOALLOC_SCRATCH_BYTES (4u << 20)
 
 namespace rg {

@@ -410,6 +410,10 @@ static rg_status time_seq(rg_program *p, const std::vector<Launch> &seq, hipStre
     return RG_OK;
 }
 
+// A candidate within this factor of the fastest counts as equally fast
+// (repeated sample timings agree within about 0.5 %).
+static constexpr float kTuneTolerance = 1.015f;
+
 // Keyed by program, integrator, ray count (power of two below it), the
 // device's architecture name and CU count, and the hipRTC version.
 static std::string tune_key(rg_program *p, const char *what, long long n) {
@@ -467,16 +471,31 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     // a shortened run of the real launch, stores included (they write the
     // caller's first snapshots and checkpoints, which the run that follows
     // overwrites): long enough to rank the candidates above timer noise
-    // Candidates in order of preference: among those within 3 % of the
-    // fastest (run-to-run noise), the first is taken, so near-equal
+    // Candidates in order of preference: among those within the tolerance
+    // of the fastest (run-to-run noise), the first is taken, so near-equal
     // configurations do not flip from one process to the next.
     rg_kargs t = a;
     t.n_steps = std::min(a.n_steps, std::max(128, std::min(1024, a.n_steps / 16)));
-    // (rays per lane, block, at-least-four-waves variant); the variant last,
-    // so that it is taken only where it is more than 3 % faster
+    // (rays per lane, block, at-least-four-waves variant).  The variant
+    // comes first where it is more occupancy for free (fewer registers than
+    // the plain kernel and no spill), else last, so that it is taken only
+    // where it is faster beyond the tolerance.
     struct Cand { int rpl, block, occ; };
-    const Cand cand[] = {{1, 256, 0}, {1, 512, 0}, {1, 128, 0}, {2, 256, 0}, {2, 128, 0}, {1, 64, 0},
-                         {2, 512, 0}, {2, 64, 0}, {4, 128, 0}, {4, 256, 0}, {1, 256, 1}, {1, 512, 1}};
+    std::vector<Cand> cand = {{1, 256, 0}, {1, 512, 0}, {1, 128, 0}, {2, 256, 0}, {2, 128, 0}, {1, 64, 0},
+                              {2, 512, 0}, {2, 64, 0}, {4, 128, 0}, {4, 256, 0}};
+    bool occ_free = false;
+    if (!fp32) {
+        hipFunction_t f1, f4;
+        int r1 = 0, r4 = 0, spill = 1;
+        if (kernel(p, "rg_rk4_r1", &f1) == RG_OK && kernel(p, "rg_rk4_r1o4", &f4) == RG_OK &&
+            hipFuncGetAttribute(&r1, HIP_FUNC_ATTRIBUTE_NUM_REGS, f1) == hipSuccess &&
+            hipFuncGetAttribute(&r4, HIP_FUNC_ATTRIBUTE_NUM_REGS, f4) == hipSuccess &&
+            hipFuncGetAttribute(&spill, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, f4) == hipSuccess)
+            occ_free = r4 < r1 && spill == 0;
+        (void)hipGetLastError();
+    }
+    const std::vector<Cand> o4 = {{1, 256, 1}, {1, 512, 1}};
+    cand.insert(occ_free ? cand.begin() : cand.end(), o4.begin(), o4.end());
     std::vector<float> ms_of;
     for (const Cand &c : cand) {
         float ms = 1e30f;
@@ -491,7 +510,7 @@ static rg_status tune_rk4(rg_program *p, const rg_kargs &a, hipStream_t s, TuneE
     const float best = *std::min_element(ms_of.begin(), ms_of.end());
     TuneEntry bt;
     for (size_t i = 0; i < ms_of.size(); i++)
-        if (ms_of[i] <= 1.03f * best) {
+        if (ms_of[i] <= kTuneTolerance * best) {
             bt.rpl = cand[i].rpl;
             bt.block = cand[i].block;
             bt.occ = cand[i].occ;
@@ -533,7 +552,7 @@ static rg_status tune_dopri(rg_program *p, const rg_kargs &a, hipStream_t s, Tun
             t.budget_cap = 400;
         }
     }
-    // (preference order and 3 % tolerance as for RK4)
+    // (preference order and tolerance as for RK4)
     const std::pair<int, int> cand[] = {{256, 8}, {128, 8}, {64, 8}, {256, 32}, {128, 32}, {64, 32},
                                         {256, 128}, {128, 128}, {64, 128}, {256, -1}, {128, -1}, {64, -1}};
     std::vector<float> ms_of;
@@ -547,7 +566,7 @@ static rg_status tune_dopri(rg_program *p, const rg_kargs &a, hipStream_t s, Tun
     const float best = *std::min_element(ms_of.begin(), ms_of.end());
     TuneEntry bt;
     for (size_t i = 0; i < ms_of.size(); i++)
-        if (ms_of[i] <= 1.03f * best) {
+        if (ms_of[i] <= kTuneTolerance * best) {
             bt.block = cand[i].first;
             bt.compact = cand[i].second;
             break;

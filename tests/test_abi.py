@@ -67,3 +67,33 @@ def test_compile_opts_struct_size_checked():
     h = C.c_void_p()
     assert rgb._lib.rg_compile(g.h, D.id, C.byref(o), C.byref(h)) == rgb.RG_EINVAL
     assert b"struct_size" in rgb._lib.rg_last_error()
+
+
+def test_trace_workspace_sizes_on_the_host():
+    """rg_workspace_size needs no GPU for traces: none for persistent RK4, the
+    per-ray state of the one-launch-per-step forms (16 B per ray for RK4,
+    y, k1, t, h, facmax, status, steps, attempts for Dormand-Prince), 8 B of
+    refill queue for persistent Dormand-Prince; zero rays need none."""
+    w = W.make("3", 8)
+    g, D, _ = media.build(w.medium)
+    prog = g.compile(D, compile_only=True)
+    ny = 2 * w.dim
+
+    def size(n, integrator, mode):
+        d = rgb.TraceDesc()
+        d.struct_size = C.sizeof(rgb.TraceDesc)
+        d.n_rays, d.integrator, d.mode = n, integrator, mode
+        b = C.c_size_t()
+        assert rgb._lib.rg_workspace_size(prog.h, C.byref(d), C.byref(b)) == rgb.RG_OK
+        return b.value
+
+    n = 1000
+    assert size(n, rgb.RK4, rgb.PERSISTENT) == 0
+    assert size(0, rgb.RK4, rgb.PLAIN) == 0
+    assert 16 * n <= size(n, rgb.RK4, rgb.PLAIN) <= 16 * n + 3 * 256
+    assert size(n, rgb.DOPRI54, rgb.PERSISTENT) == 8
+    per_ray = 8 * (2 * ny + 3) + 4 * 3
+    assert per_ray * n <= size(n, rgb.DOPRI54, rgb.PLAIN) <= per_ray * n + 10 * 256
+    small = rgb.TraceDesc()
+    small.struct_size = 4
+    assert rgb._lib.rg_workspace_size(prog.h, C.byref(small), C.byref(C.c_size_t())) == rgb.RG_EINVAL
