@@ -14,8 +14,14 @@ class _RayTraceFn(torch.autograd.Function):
     def forward(ctx, tracer, x0, k0, omega, *params):
         x0, k0, omega = x0.detach().contiguous(), k0.detach().contiguous(), omega.detach().contiguous()
         params = [p.detach().contiguous() for p in params]
+        # with store_checkpoints=False the forward keeps no checkpoints: the
+        # adjoint reruns it inside its own call (checkpoints = NULL), trading
+        # one more forward for the checkpoint memory until backward
+        ce = tracer.checkpoint_every if tracer.store_checkpoints else 0
         out = tracer.prog.trace(x0, k0, omega, params, dt=tracer.dt, n_steps=tracer.n_steps,
-                                checkpoint_every=tracer.checkpoint_every, **tracer.launch)
+                                checkpoint_every=ce, **tracer.launch)
+        if not tracer.store_checkpoints:
+            out["_desc"].checkpoint_every = tracer.checkpoint_every  # checkpoints stay NULL
         ctx.tracer = tracer
         ctx.keep = (out, x0, k0, omega, params)  # device buffers the descriptor points to
         return out["x"], out["k"]
@@ -36,14 +42,18 @@ class _RayTraceFn(torch.autograd.Function):
 
 class RayTracer:
     """Callable ray tracer for a medium: (x0, k0, omega, *params) -> (x_end, k_end),
-    differentiable in x0, k0 and the parameter arrays."""
+    differentiable in x0, k0 and the parameter arrays.  store_checkpoints=False
+    keeps no forward checkpoints between forward and backward (the adjoint
+    reruns the forward)."""
 
-    def __init__(self, medium, dt: float, n_steps: int, checkpoint_every: int = 100, **launch):
+    def __init__(self, medium, dt: float, n_steps: int, checkpoint_every: int = 100,
+                 store_checkpoints: bool = True, **launch):
         g, D, params = media.build(medium)
         self.graph, self.D = g, D
         self.prog = g.compile(D, want_adjoint=True)
         self.default_params = params
         self.dt, self.n_steps, self.checkpoint_every = dt, n_steps, checkpoint_every
+        self.store_checkpoints = store_checkpoints
         self.launch = launch
 
     def __call__(self, x0, k0, omega, *params):

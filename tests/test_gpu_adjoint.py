@@ -192,6 +192,14 @@ def test_autograd_function_matches_adjoint():
     loss.backward()
     assert np.allclose(k0r.grad.cpu().numpy(), g["gk0"], rtol=0, atol=1e-13)
     assert np.allclose(coef.grad.cpu().numpy(), g["gp"][0], rtol=1e-12, atol=1e-13)
+    # without stored checkpoints (the adjoint reruns the forward): same gradients
+    lean = RayTracer(w.medium, dt=w.dt, n_steps=w.n_steps, checkpoint_every=100, store_checkpoints=False)
+    k0s = k0.clone().requires_grad_(True)
+    cs = g["pt"][0].clone().requires_grad_(True)
+    xe, _ = lean(x0, k0s, om, cs)
+    ((xe - U.dev(w.targets)) ** 2).sum().backward()
+    assert np.array_equal(k0s.grad.cpu().numpy(), k0r.grad.cpu().numpy())
+    assert np.allclose(cs.grad.cpu().numpy(), coef.grad.cpu().numpy(), rtol=1e-12, atol=1e-13)
 
 
 def test_aniso_full_size_sampled(oracle):
