@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <algorithm>
 #include <map>
 #include <sstream>
@@ -84,7 +85,22 @@ struct Emitter {
     bool cur_inv = false;            // the operation being counted is ray-invariant
 
     const char *T() const { return f32 ? "float" : "double"; }
-    std::string lit(double v) const { return f32 ? hex_float(v) : hex_double(v); }
+    std::vector<double> *ktab = nullptr;  // FunctionSpec::const_table
+    // Inline FP64 operands of gfx9 instructions: 0, +-0.5, +-1, +-2, +-4
+    // and the integers -16..64 (1/(2 pi) is one too but never a graph constant).
+    static bool inline_f64(double v) {
+        if (v == 0.5 || v == -0.5 || v == 2.0 || v == -2.0 || v == 4.0 || v == -4.0) return true;
+        return v == std::floor(v) && v >= -16.0 && v <= 64.0;
+    }
+    std::string lit(double v) const {
+        if (f32) return hex_float(v);
+        if (!ktab || !std::isfinite(v) || inline_f64(v)) return hex_double(v);
+        size_t i = 0;
+        for (; i < ktab->size(); i++)
+            if (std::memcmp(&(*ktab)[i], &v, sizeof v) == 0) break;
+        if (i == ktab->size()) ktab->push_back(v);
+        return "RG_KV(" + std::to_string(i) + ", " + hex_double(v) + ")";
+    }
     std::string fn(const char *base) const { return f32 ? std::string(base) + "f" : std::string(base); }
 
     Emitter(const Graph &g_, const std::vector<int> &ts) : g(g_), table_slot(ts) {
@@ -703,6 +719,7 @@ std::string emit_function(const Graph &g, const FunctionSpec &spec,
     Emitter em(g, param_table_slot);
     em.f32 = spec.fp32;
     em.inv_state = spec.inv_state;
+    em.ktab = spec.fp32 ? nullptr : spec.const_table;
     if (spec.fp32 && !spec.spline_seeds.empty()) throw std::invalid_argument("single precision VJP");
     std::vector<uint32_t> roots;
     for (const Output &o : spec.outputs) roots.push_back(o.node);
@@ -713,6 +730,7 @@ std::string emit_function(const Graph &g, const FunctionSpec &spec,
     std::vector<uint32_t> order = g.reachable(roots);
     em.plan(order, roots);
     em.os << spec.signature << "\n";
+    if (em.ktab) em.os << "  RG_KBASE\n";
     std::vector<char> out_done(spec.outputs.size(), 0);
     em.schedule_and_emit(order, roots, spec.returns_value ? nullptr : &spec.outputs, &out_done);
     if (!spec.spline_seeds.empty()) em.emit_spline_grads(spec.spline_seeds);

@@ -55,6 +55,11 @@ struct FunctionSpec {
     bool returns_value = false;            // single output via "return"
     bool fp32 = false;                     // single precision (no spline nodes)
     uint32_t inv_state = 0;                // state components constant along a ray (bit c: y[c])
+    // FP64 constants that are not inline operands of the instruction set are
+    // entered in this table (shared by the functions of a program) and
+    // written RG_KV(i, literal): entry i of the table, or the literal where
+    // the function's RG_KL flag is set; null: literals only.
+    std::vector<double> *const_table = nullptr;
 };
 
 // Emit a function.  `tables` maps a spline-definition's parameter to a table

@@ -440,7 +440,9 @@ struct rg_dp_ray {
 };
 
 // One Dormand-Prince attempt with the termination tests that precede and
-// follow it.  Sets r.st >= 0 when the ray is finished.
+// follow it.  Sets r.st >= 0 when the ray is finished.  Its seven right-hand sides
+// are inlined one after the other and take their constants as literals
+// (rg_rhs<true>), which the compiler keeps in scalar registers across them.
 __device__ __forceinline__ void rg_dp_attempt(const rg_kargs &a, const rg_P &P, rg_dp_ray &r) {
     if (r.acc >= r.budget || r.att >= 4 * r.budget) { r.st = RG_RAY_BUDGET; return; }
     if (a.t_end > 0.0 && r.t >= a.t_end) { r.st = RG_RAY_OK; return; }
@@ -449,23 +451,23 @@ __device__ __forceinline__ void rg_dp_attempt(const rg_kargs &a, const rg_P &P, 
     double k2[RG_NY], k3[RG_NY], k4[RG_NY], k5[RG_NY], k6[RG_NY], k7[RG_NY], Y[RG_NY];
     const double *y = r.y, *k1 = r.k1;
     for (int i = 0; i < RG_NY; i++) Y[i] = fma(hs, DPA21 * k1[i], y[i]);
-    rg_rhs(Y, r.om, r.t + hs * (1.0 / 5.0), P, k2);
+    rg_rhs<true>(Y, r.om, r.t + hs * (1.0 / 5.0), P, k2);
     for (int i = 0; i < RG_NY; i++) Y[i] = fma(hs, fma(DPA32, k2[i], DPA31 * k1[i]), y[i]);
-    rg_rhs(Y, r.om, r.t + hs * (3.0 / 10.0), P, k3);
+    rg_rhs<true>(Y, r.om, r.t + hs * (3.0 / 10.0), P, k3);
     for (int i = 0; i < RG_NY; i++)
         Y[i] = fma(hs, fma(DPA43, k3[i], fma(DPA42, k2[i], DPA41 * k1[i])), y[i]);
-    rg_rhs(Y, r.om, r.t + hs * (4.0 / 5.0), P, k4);
+    rg_rhs<true>(Y, r.om, r.t + hs * (4.0 / 5.0), P, k4);
     for (int i = 0; i < RG_NY; i++)
         Y[i] = fma(hs, fma(DPA54, k4[i], fma(DPA53, k3[i], fma(DPA52, k2[i], DPA51 * k1[i]))), y[i]);
-    rg_rhs(Y, r.om, r.t + hs * (8.0 / 9.0), P, k5);
+    rg_rhs<true>(Y, r.om, r.t + hs * (8.0 / 9.0), P, k5);
     for (int i = 0; i < RG_NY; i++)
         Y[i] = fma(hs, fma(DPA65, k5[i], fma(DPA64, k4[i], fma(DPA63, k3[i], fma(DPA62, k2[i], DPA61 * k1[i])))), y[i]);
-    rg_rhs(Y, r.om, r.t + hs, P, k6);
+    rg_rhs<true>(Y, r.om, r.t + hs, P, k6);
     // 5th-order solution (also the 7th stage point, FSAL)
     double y5[RG_NY];
     for (int i = 0; i < RG_NY; i++)
         y5[i] = fma(hs, fma(DPB6, k6[i], fma(DPB5, k5[i], fma(DPB4, k4[i], fma(DPB3, k3[i], DPB1 * k1[i])))), y[i]);
-    rg_rhs(y5, r.om, r.t + hs, P, k7);
+    rg_rhs<true>(y5, r.om, r.t + hs, P, k7);
     double sum = 0.0;
     for (int i = 0; i < RG_NY; i++) {
         double e = fma(DPE7, k7[i], fma(DPE6, k6[i], fma(DPE5, k5[i], fma(DPE4, k4[i], fma(DPE3, k3[i], DPE1 * k1[i])))));
@@ -565,7 +567,7 @@ extern "C" __global__ void __launch_bounds__(512) rg_dopri_persistent(rg_kargs a
         iter++;
         if (alive) {
             if (need_k1) {
-                rg_rhs(r.y, r.om, r.t, P, r.k1);
+                rg_rhs<true>(r.y, r.om, r.t, P, r.k1);
                 need_k1 = false;
             }
             rg_dp_attempt(a, P, r);
@@ -586,7 +588,7 @@ extern "C" __global__ void __launch_bounds__(512) rg_dopri_plain_init(rg_kargs a
     const rg_P P = rg_params(a);
     rg_dp_ray r;
     rg_dp_load(a, P, id, r);
-    rg_rhs(r.y, r.om, r.t, P, r.k1);
+    rg_rhs<true>(r.y, r.om, r.t, P, r.k1);
     for (int c = 0; c < RG_NY; c++) {
         a.s_y[(long long)c * n + id] = r.y[c];
         a.s_k1[(long long)c * n + id] = r.k1[c];

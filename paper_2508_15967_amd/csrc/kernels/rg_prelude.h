@@ -9,6 +9,23 @@
 
 #define RG_MAX_PARAMS 8
 
+// Constant table of functions with many FP64 constants: the emitted code
+// writes RG_KV(i, literal), entry i of the table rg_ktab unless the
+// function's template flag RG_KL asks for the literal.  On the device the
+// table is read through the scalar cache, one wide load fetching up to
+// eight constants, from a base pointer made opaque at each call so that the
+// loads stay in the loop that uses them instead of being hoisted into scalar
+// registers for the whole kernel.  Host builds define RG_KTAB and RG_KBASE
+// themselves.
+#define RG_KV(i, v) (RG_KL ? (v) : rg_k[i])
+#ifndef RG_KTAB
+#define RG_KTAB __constant__
+typedef const __attribute__((address_space(4))) double rg_kd;
+#define RG_KBASE                    \
+    rg_kd *rg_k = (rg_kd *)rg_ktab; \
+    if (!RG_KL) __asm__ volatile("" : "+s"(rg_k));
+#endif
+
 // Parameter arrays (device pointers, in declaration order).
 struct rg_P {
     const double *p[RG_MAX_PARAMS];

@@ -201,10 +201,21 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
 
     // ---- emit rhs and D
     std::ostringstream fs;
+    // Rolled programs read their FP64 constants from one table through the
+    // scalar cache: a wide load brings several constants where each literal
+    // costs two scalar moves per use (about a third of the instructions of
+    // a rolled RK4 stage).  Every FP64 function takes a template flag
+    // RG_KL that turns the table reads back into literals (the
+    // Dormand-Prince attempt, whose seven inlined right-hand sides keep
+    // literals in scalar registers across stages).
+    std::vector<double> ktab;
+    std::vector<double> *kt = p->rolled ? &ktab : nullptr;
     Flops fl_rhs, fl_rhs_dp, fl_D, fl_vjp, fl_rhs_vjp;
     {
         FunctionSpec spec;
+        spec.const_table = kt;
         spec.signature =
+            "template <bool RG_KL = false>\n"
             "RG_FN void rg_rhs(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, double *__restrict__ f) {\n  (void)om; (void)t; (void)P;";
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
@@ -224,6 +235,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             if (g.node(n).op == SPLINE)
                 return fail(RG_EUNSUPPORTED, "single precision right-hand side with spline nodes");
         FunctionSpec spec;
+        spec.const_table = kt;
         spec.fp32 = true;
         spec.signature =
             "RG_FN void rg_rhs(const float *__restrict__ y, const float om, const float t, "
@@ -237,7 +249,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     }
     {
         FunctionSpec spec;
+        spec.const_table = kt;
         spec.signature =
+            "template <bool RG_KL = false>\n"
             "RG_FN double rg_D(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
@@ -248,7 +262,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
     {
         // D and dD/dk (Newton solve for launch conditions)
         FunctionSpec spec;
+        spec.const_table = kt;
         spec.signature =
+            "template <bool RG_KL = false>\n"
             "RG_FN void rg_Dk(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, double *__restrict__ out) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "out[0]", false});
@@ -269,8 +285,9 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         const std::vector<uint32_t> adj = g.adjoints(f, seeds);
         auto A = [&](uint32_t n) { return adj[n] == NONE ? g.constant(0.0) : adj[n]; };
         FunctionSpec spec;
+        spec.const_table = kt;
         spec.signature =
-            "template <typename GPT>\nRG_FN void rg_vjp(const double *__restrict__ y, const double om, const double t, "
+            "template <typename GPT, bool RG_KL = false>\nRG_FN void rg_vjp(const double *__restrict__ y, const double om, const double t, "
             "const rg_P &P, const double *__restrict__ av, double *__restrict__ jv, "
             "GPT gp, rg_GA &G) {\n  (void)om; (void)t; (void)P; (void)gp; (void)G;";
         for (uint32_t j = 0; j < ny; j++) spec.outputs.push_back({A(yv[j]), "jv[" + std::to_string(j) + "]", false});
@@ -298,7 +315,15 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         factor_spec(g, both, !p->rolled);
         emit_function(g, both, table_slot, &fl_rhs_vjp);
     }
-    p->functions_src = fs.str();
+    if (!ktab.empty()) {
+        std::ostringstream kd;
+        kd << "RG_KTAB double rg_ktab[" << ktab.size() << "] = {";
+        for (size_t i = 0; i < ktab.size(); i++) kd << (i ? ", " : "") << hex_double(ktab[i]);
+        kd << "};\n";
+        p->functions_src = kd.str() + fs.str();
+    } else {
+        p->functions_src = fs.str();
+    }
     // The adjoint recomputes the stage states Y2..Y4 where three right-hand
     // sides cost less than waiting for them from the segment buffer (a few
     // hundred issued flops against a global-memory latency the few waves of

@@ -20,6 +20,8 @@ HOST_HARNESS = r'''
 #include <math.h>
 #include <string.h>
 #define RG_FN static inline
+#define RG_KTAB static const
+#define RG_KBASE const double *rg_k = rg_ktab;
 #include "rg_prelude.h"
 static const double *g_tab[8];
 static int g_tab_ny[8];
