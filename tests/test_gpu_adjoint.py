@@ -204,7 +204,7 @@ def test_autograd_function_matches_adjoint():
 
 def test_aniso_full_size_sampled(oracle):
     """Full workload 5 (1,048,576 rays, 20,000 steps, checkpoints every
-    100) forward and adjoint in the benchmark's launch configuration; the
+    10) forward and adjoint in the benchmark's launch configuration; the
     endpoints and the per-ray gradients dL/dx0, dL/dk0 of 96 sampled rays
     recomputed by the oracle (the parameter gradient sums all rays and is
     checked at smaller sizes above)."""
