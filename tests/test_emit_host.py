@@ -47,6 +47,19 @@ extern "C" void host_eval(int n, int ny, const double *y, const double *om, cons
         D[r] = rg_D(yy, om[r], 0.0, P);
     }
 }
+// the same functions with the constants as literals (RG_KL)
+extern "C" void host_eval_lit(int n, int ny, const double *y, const double *om, const double *const *pp,
+                              double *f, double *D) {
+    rg_P P; memset(&P, 0, sizeof P);
+    for (int i = 0; i < 8 && pp; i++) P.p[i] = pp[i];
+    for (int r = 0; r < n; r++) {
+        double yy[6], ff[6];
+        for (int c = 0; c < ny; c++) yy[c] = y[c * n + r];
+        rg_rhs<true>(yy, om[r], 0.0, P, ff);
+        for (int c = 0; c < ny; c++) f[c * n + r] = ff[c];
+        D[r] = rg_D<true>(yy, om[r], 0.0, P);
+    }
+}
 #ifdef HAS_F32
 extern "C" void host_eval32(int n, int ny, const float *y, const float *om, const double *const *pp,
                             float *f) {
@@ -148,6 +161,37 @@ def test_emitted_functions_match_oracle(oracle, cfg):
             go = oracle.param_vjp_points(w.medium, y, om, v)
             got = grad if cfg == "4" else gp[:16]
             assert np.abs(got - go).max() / np.abs(go).max() < 1e-12
+
+
+@pytest.mark.parametrize("cfg", ["2", "3", "5"])
+def test_constant_table_equals_literals(cfg):
+    """Programs with many constants (the bumps and the anisotropic medium)
+    read their FP64 constants from one table; the same functions with the
+    RG_KL flag take them as literals.  Both forms hold the same doubles, so
+    the results are bitwise equal; programs with few constants keep
+    literals only."""
+    from paper_2508_15967_amd import media
+    w = W.make(cfg, 2048)
+    g, D, params = media.build(w.medium)
+    prog = g.compile(D, compile_only=True)
+    src = prog.functions()
+    rolled = cfg in ("3", "5")
+    assert ("rg_ktab[" in src) == rolled and ("RG_KV(" in src) == rolled
+    rng = np.random.default_rng(5)
+    n = 300
+    y, om = _points(w, n, rng)
+    ny = 2 * w.dim
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, False, tmp)
+        pp = _ptrs(params)
+        out = []
+        for fn in (lib.host_eval, lib.host_eval_lit):
+            f, Dv = np.zeros((ny, n)), np.zeros(n)
+            fn(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
+               C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+            out.append((f, Dv))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.isfinite(out[0][0]).all()
 
 
 @pytest.mark.parametrize("cfg", ["1", "2", "3", "5", "cO", "cX", "cO2"])
