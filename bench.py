@@ -289,6 +289,18 @@ class Bench:
         out = {"value": psteps / pw, "ms_per_trace": pw * 1e3,
                "launches_per_trace": self.w.n_steps + 2 if self.w.integrator == self.W.RK4 else None,
                "speedup_vs_plain": (pw * 1e3 / psteps) / (self.fwd_ms / self.ray_steps)}
+        if self.w.integrator == self.W.RK4 and psteps == self.w.n * self.w.n_steps:
+            # every launch reads and writes each ray's state (2 dim doubles),
+            # t, status and step count and reads omega; plus the stored
+            # snapshots and checkpoints
+            ny = 2 * self.w.dim
+            b = 16 * ny + 40
+            if self.w.store_every > 0:
+                b += 8 * ny / self.w.store_every
+            if self.adjoint:
+                b += 8 * (ny + 1) / self.w.ckpt_every
+            out["alg_bytes_per_ray_step"] = b
+            out["hbm_gbs_alg"] = b * psteps / pw / 1e9
         if self.adjoint:
             # the adjoint in its per-step form on the plain forward's checkpoints
             self.bwd(pdesc)
