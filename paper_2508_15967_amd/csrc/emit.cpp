@@ -80,6 +80,10 @@ struct Emitter {
     std::vector<uint32_t> consumer;  // unique consumer of a single-use node
     bool f32 = false;                // emit single precision (float) code
     std::vector<signed char> sgn;    // 1: value >= 0, -1: <= 0 (or NaN), 0: not known
+    // Finite-input analysis (inputs: state, omega, t, parameters): fin, the
+    // value is finite whenever the inputs are (no overflow possible); nnan,
+    // it is not NaN whenever the inputs are finite.
+    std::vector<char> fin, nnan;
     std::vector<char> inv;           // value depends only on constants, parameters, omega
     uint32_t inv_state = 0;          // and these state components (constant along a ray)
     bool cur_inv = false;            // the operation being counted is ray-invariant
@@ -194,6 +198,60 @@ struct Emitter {
             default: break;
             }
             sgn[n] = (signed char)s;
+        }
+        // NaN arises only from inf - inf, 0 * inf, 0 / 0, inf / inf, the
+        // square root or logarithm of a negative number, or the sine or
+        // cosine of an infinity; overflow only from operations that can
+        // grow a finite value.  The rules below claim a property only where
+        // none of these can happen; everything else is left unclaimed.
+        fin.assign(g.size(), 0);
+        nnan.assign(g.size(), 0);
+        auto is_const = [&](uint32_t m) { return m != NONE && g.node(m).op == CONST; };
+        auto cval = [&](uint32_t m) { return g.node(m).val; };
+        auto nz_const = [&](uint32_t m) { return is_const(m) && cval(m) != 0.0 && std::isfinite(cval(m)); };
+        for (uint32_t n : order) {
+            const Node &nd = g.node(n);
+            auto S = [&](uint32_t m) { return m == NONE ? 0 : (int)sgn[m]; };
+            const bool fa = nd.a != NONE && fin[nd.a], fb = nd.b != NONE && fin[nd.b];
+            const bool na = nd.a != NONE && nnan[nd.a], nb = nd.b != NONE && nnan[nd.b];
+            bool F = false, N = false;
+            switch (nd.op) {
+            case CONST: F = N = std::isfinite(nd.val); break;
+            case VAR: case PARAM: F = N = true; break;
+            case NEG: F = fa; N = na; break;
+            case ADD: case SUB: {
+                // infinities of one direction add without NaN: operands of
+                // one proven sign (ADD), of opposite signs (SUB)
+                const int sa = S(nd.a), sb = S(nd.b);
+                const bool one_dir = sa != 0 && (nd.op == ADD ? sa == sb : sa == -sb);
+                N = na && nb && (fa || fb || one_dir);
+                // a finite value plus a constant below half an ulp of the
+                // largest double rounds to at most that double
+                auto small = [&](uint32_t m) { return is_const(m) && std::fabs(cval(m)) <= 0x1p969; };
+                F = (fa && small(nd.b)) || (fb && small(nd.a));
+                break;
+            }
+            case MUL:
+                // finite * finite may overflow but is not NaN; a nonzero
+                // constant times an infinity is an infinity; x * x >= 0
+                N = na && nb && ((fa && fb) || nz_const(nd.a) || nz_const(nd.b) || nd.a == nd.b);
+                F = (fa && is_const(nd.b) && std::fabs(cval(nd.b)) <= 1.0) ||
+                    (fb && is_const(nd.a) && std::fabs(cval(nd.a)) <= 1.0);
+                break;
+            case DIV:
+                // c / x (x = 0: inf, x = inf: 0) and x / c, c a nonzero constant
+                N = (nz_const(nd.a) && nb) || (nz_const(nd.b) && na);
+                F = fa && nz_const(nd.b) && std::fabs(cval(nd.b)) >= 1.0;
+                break;
+            case EXP: N = na; F = na && S(nd.a) < 0; break;
+            case SQRT: N = na && S(nd.a) > 0; F = N && fa; break;
+            case LOG: N = na && S(nd.a) > 0; break;
+            case SIN: case COS: F = N = fa; break;
+            case POWI: N = na; break;  // x^k, 1/x^k: 0 and inf give 0 or inf
+            default: break;            // spline nodes: not claimed
+            }
+            fin[n] = F;
+            nnan[n] = N;
         }
         inv.assign(g.size(), 0);
         for (uint32_t n : order) {
@@ -377,9 +435,10 @@ struct Emitter {
             break;
         case NEG: e = "-" + A; break;
         case EXP:
-            // the argument proved non-positive (a Gaussian's exponent, say):
-            // the variant without the upper clamp
-            e = (f32 ? "expf(" : sgn[nd.a] < 0 ? "rg_exp_np(" : "rg_exp(") + A + ")";
+            // an argument that is not NaN for finite inputs: the variant
+            // whose lower clamp is a maximum (NaN -> 0); proven
+            // non-positive as well: also without the overflow clamp
+            e = (f32 ? "expf(" : !nnan[nd.a] ? "rg_exp(" : sgn[nd.a] < 0 ? "rg_exp_np(" : "rg_exp_nn(") + A + ")";
             count(EXP);
             break;
         case LOG: e = fn("log") + "(" + A + ")"; count(LOG); break;

@@ -468,9 +468,15 @@ __device__ __forceinline__ void rg_dp_attempt(const rg_kargs &a, const rg_P &P, 
     for (int i = 0; i < RG_NY; i++)
         y5[i] = fma(hs, fma(DPB6, k6[i], fma(DPB5, k5[i], fma(DPB4, k4[i], fma(DPB3, k3[i], DPB1 * k1[i])))), y[i]);
     rg_rhs<true>(y5, r.om, r.t + hs, P, k7);
+    // k2 has weight 0 in both solutions; its 0 * k2 term makes the error
+    // estimate NaN when k2 is not finite, so that the attempt is rejected
+    // like one whose stage states are not finite (a stage right-hand side
+    // may be finite at a non-finite state: NaN-free exponentials map a NaN
+    // argument to 0)
     double sum = 0.0;
     for (int i = 0; i < RG_NY; i++) {
-        double e = fma(DPE7, k7[i], fma(DPE6, k6[i], fma(DPE5, k5[i], fma(DPE4, k4[i], fma(DPE3, k3[i], DPE1 * k1[i])))));
+        double e = fma(DPE7, k7[i], fma(DPE6, k6[i], fma(DPE5, k5[i], fma(DPE4, k4[i], fma(DPE3, k3[i],
+                   fma(0.0, k2[i], DPE1 * k1[i]))))));
         e = hs * e;
         const double ay = fabs(y[i]), ay5 = fabs(y5[i]);
         const double sc = fma(a.rtol, ay > ay5 ? ay : ay5, a.atol);

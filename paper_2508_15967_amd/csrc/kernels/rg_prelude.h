@@ -135,25 +135,28 @@ RG_FN double rg_rcp(double d) {
     0x1.fa7c1819e90d8p+0, 0x1.fbdba3692d514p+0, 0x1.fd3c22b8f71f1p+0, 0x1.fe9d96b2a23d9p+0
 // RG_EXP_TABLE end
 
-// kNonPos: the caller guarantees x <= 0 or NaN (the emitter proves it from
-// the graph), so the upper clamp, whose only role is to keep n in range for
-// x > 1100, is left out, and the lower clamp is a plain maximum, which maps
-// a NaN argument to -1100 and so to e^x = 0 (one instruction against a
-// compare and two selects).  A proven non-positive argument is NaN only
-// when the stage state it is computed from is (its sums have terms of one
-// sign, so no inf - inf); the step or attempt through that state is then
-// non-finite in the state's own NaN component and is rejected, with the
-// same outcome whatever the exponential returned.
-template <bool kNonPos>
+// kMode 0 (rg_exp): any argument; a NaN argument gives NaN.
+// kMode 1 (rg_exp_nn): the argument is not NaN while the stage state, omega,
+// t and the parameters are finite (the emitter proves it from the graph).
+// The lower clamp is then a plain maximum, which maps a NaN argument to
+// -1100 and so to e^x = 0 (one instruction against a compare and two
+// selects).  Such a NaN comes from a non-finite stage state, and a
+// non-finite stage state makes the step or attempt through it non-finite
+// or its error estimate NaN, so it is rejected with the same outcome
+// whatever the exponential returned.
+// kMode 2 (rg_exp_np): as 1 and the argument is also proven <= 0, so the
+// upper clamp, whose only role is to keep n in range for x > 1100, is left
+// out as well.
+template <int kMode>
 RG_FN double rg_exp_tab(double x, const double *tab) {
     // below -1100 the result is 0 (the general form's select keeps NaN);
     // above 1100 n stays bounded while r grows with x, so the result
     // overflows to +inf, and a NaN reaches r and the result
-    x = kNonPos ? fmax(x, -1100.0) : (x < -1100.0 ? -1100.0 : x);
+    x = kMode > 0 ? fmax(x, -1100.0) : (x < -1100.0 ? -1100.0 : x);
     // n = x N/ln2 rounded to nearest (even) by adding 1.5 2^52, whose ulp is
     // 1: the sum holds n in its low 32 bits (two's complement), and
     // subtracting the constant again gives n as a double
-    const double s = fma(kNonPos ? x : fmin(x, 1100.0), RG_EXP_INV_L, 0x1.8p52);
+    const double s = fma(kMode == 2 ? x : fmin(x, 1100.0), RG_EXP_INV_L, 0x1.8p52);
     const double n = s - 0x1.8p52;
     double r = fma(-n, RG_EXP_L1, x);
     r = fma(-n, RG_EXP_L2, r);
@@ -169,12 +172,14 @@ RG_FN double rg_exp_tab(double x, const double *tab) {
 #if defined(__HIPCC__) || defined(__HIPCC_RTC__)
 // the table lives in LDS; every kernel that calls rg_exp stages it first
 __shared__ double rg_exp_lds[RG_EXP_N];
-RG_FN double rg_exp(double x) { return rg_exp_tab<false>(x, rg_exp_lds); }
-RG_FN double rg_exp_np(double x) { return rg_exp_tab<true>(x, rg_exp_lds); }
+RG_FN double rg_exp(double x) { return rg_exp_tab<0>(x, rg_exp_lds); }
+RG_FN double rg_exp_nn(double x) { return rg_exp_tab<1>(x, rg_exp_lds); }
+RG_FN double rg_exp_np(double x) { return rg_exp_tab<2>(x, rg_exp_lds); }
 #else
 static const double rg_exp_host_tab[RG_EXP_N] = {RG_EXP_TABLE_VALUES};
-RG_FN double rg_exp(double x) { return rg_exp_tab<false>(x, rg_exp_host_tab); }
-RG_FN double rg_exp_np(double x) { return rg_exp_tab<true>(x, rg_exp_host_tab); }
+RG_FN double rg_exp(double x) { return rg_exp_tab<0>(x, rg_exp_host_tab); }
+RG_FN double rg_exp_nn(double x) { return rg_exp_tab<1>(x, rg_exp_host_tab); }
+RG_FN double rg_exp_np(double x) { return rg_exp_tab<2>(x, rg_exp_host_tab); }
 #endif
 
 // Single precision reciprocal: the hardware estimate and one Newton step

@@ -267,14 +267,42 @@ def test_exp_table_matches_generator():
     assert gen.block() in text
 
 
+def _exp_variant_programs(compile_only=True):
+    """D = omega e^(x0 e^x1), whose argument can be NaN at finite inputs
+    (0 * inf), takes the general rg_exp; D = omega e^x0, whose argument is
+    NaN only at a NaN input, the NaN-free variant rg_exp_nn.  At x1 = 0 and
+    omega = 1 both are e^x0 (e^0 = 1 exactly)."""
+    from paper_2508_15967_amd import raygraph as rgb
+    g = rgb.Graph(2)
+    gen = g.compile(g.omega * (g.x(0) * g.x(1).exp()).exp(), compile_only=compile_only)
+    g2 = rgb.Graph(2)
+    nn = g2.compile(g2.omega * g2.x(0).exp(), compile_only=compile_only)
+    assert "rg_exp(" in gen.functions() and "rg_exp_n" not in gen.functions().split("rg_exp(", 1)[1].split(";")[0]
+    assert "rg_exp_nn(" in nn.functions() and "rg_exp(" not in nn.functions()
+    return gen, nn
+
+
+def _check_exp_values(Dv, x, special, nan_gives_zero):
+    ulps = _exp_ulps(Dv[:x.size], _exp_reference(x))
+    assert ulps.max() <= 1.5, ulps.max()
+    got_sp = Dv[x.size:]
+    with np.errstate(over="ignore"):
+        ref_sp = np.exp(special)
+    if nan_gives_zero:
+        ref_sp = np.where(np.isnan(special), 0.0, ref_sp)
+    same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
+    # the finite specials are compared within the same bound
+    fin = np.isfinite(ref_sp) & (ref_sp > 0)
+    same |= fin & (_exp_ulps(got_sp, ref_sp) <= 1.5)
+    assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+
+
 def test_exp_host_accuracy():
     """rg_exp (table-driven, host build of the same code) within 1.5 ulp of
     the correctly rounded e^x, and exact special cases: overflow to +inf,
-    underflow to 0, e^(+-inf), NaN."""
-    from paper_2508_15967_amd import raygraph as rgb
-    g = rgb.Graph(2)
-    D = g.omega * g.x(0).exp()   # D = omega e^x0, evaluated at omega = 1
-    prog = g.compile(D, compile_only=True)
+    underflow to 0, e^(+-inf), NaN.  The NaN-free variant gives the same
+    doubles everywhere but at a NaN argument, where it gives 0."""
+    gen, nn = _exp_variant_programs()
     rng = np.random.default_rng(17)
     x, special = _exp_points(rng, 5000)
     xs = np.concatenate([x, special])
@@ -283,23 +311,19 @@ def test_exp_host_accuracy():
     y[0] = xs
     y[2] = 1.0
     om = np.ones(n)
-    with tempfile.TemporaryDirectory() as tmp:
-        lib = _host_lib(prog, False, tmp)
-        f = np.zeros((4, n))
-        Dv = np.zeros(n)
-        lib.host_eval(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), _ptrs([]),
-                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
-    ref = _exp_reference(x)
-    ulps = _exp_ulps(Dv[:x.size], ref)
-    assert ulps.max() <= 1.5, ulps.max()
-    got_sp = Dv[x.size:]
-    with np.errstate(over="ignore"):
-        ref_sp = np.exp(special)
-    same = (got_sp == ref_sp) | (np.isnan(got_sp) & np.isnan(ref_sp))
-    # the finite specials are compared within the same bound
-    fin = np.isfinite(ref_sp) & (ref_sp > 0)
-    same |= fin & (_exp_ulps(got_sp, ref_sp) <= 1.5)
-    assert same.all(), list(zip(special[~same], got_sp[~same], ref_sp[~same]))
+    out = []
+    for prog in (gen, nn):
+        with tempfile.TemporaryDirectory() as tmp:
+            lib = _host_lib(prog, False, tmp)
+            f = np.zeros((4, n))
+            Dv = np.zeros(n)
+            lib.host_eval(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), _ptrs([]),
+                          C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+        out.append(Dv)
+    _check_exp_values(out[0], x, special, nan_gives_zero=False)
+    _check_exp_values(out[1], x, special, nan_gives_zero=True)
+    num = ~np.isnan(xs)
+    assert np.array_equal(out[0][num], out[1][num])
 
 
 def test_ray_invariant_flops_counted_apart():
@@ -320,11 +344,15 @@ def test_ray_invariant_flops_counted_apart():
 
 
 def test_exp_of_nonpositive_argument():
-    """An exponential whose argument the graph proves non-positive (here
-    -x0^2, -(x0^2 + x1^2)/3) is emitted as the variant without the upper
-    clamp, others (x0, x0^2, -omega x0^2 with omega of unknown sign) as the
-    general one; the variant is within 1.5 ulp of the correctly rounded
-    e^(-x0^2), exact at 0, underflow and +-inf, and 0 at a NaN argument."""
+    """The variant of each exponential: an argument that cannot be NaN at
+    finite inputs and that the graph proves non-positive (-x0^2,
+    -(x0^2 + x1^2)/3) takes rg_exp_np, without the overflow clamp; one that
+    cannot be NaN but has no proven sign (x0, x0^2, the Chapman form
+    1 + w - e^w) rg_exp_nn; one that can be NaN at finite inputs (x0 e^x1
+    and -omega x0^2: 0 * inf, sqrt(x0), 1/x0 - 1/x1: inf - inf) the general
+    rg_exp.  rg_exp_np is within 1.5 ulp of the
+    correctly rounded e^(-x0^2), exact at 0, underflow and +-inf, and 0 at
+    a NaN argument."""
     from paper_2508_15967_amd import raygraph as rgb
 
     def src(expr_of):
@@ -332,12 +360,18 @@ def test_exp_of_nonpositive_argument():
         x, y = g.x(0), g.x(1)
         return g.compile(g.omega * expr_of(g, x, y), compile_only=True).functions()
 
-    assert "rg_exp_np(" in src(lambda g, x, y: (-(x * x)).exp())
-    assert "rg_exp_np(" in src(lambda g, x, y: (-(x * x + y * y) / 3.0).exp())
+    def variants(s):
+        return {v for v in ("rg_exp(", "rg_exp_nn(", "rg_exp_np(") if v in s}
+
+    for f in (lambda g, x, y: (-(x * x)).exp(), lambda g, x, y: (-(x * x + y * y) / 3.0).exp()):
+        assert variants(src(f)) == {"rg_exp_np("}
     for f in (lambda g, x, y: x.exp(), lambda g, x, y: (x * x).exp(),
+              lambda g, x, y: (1.0 + (-0.5 * x) - (-0.5 * x).exp()).exp()):
+        assert variants(src(f)) == {"rg_exp_nn("}, src(f)
+    for f in (lambda g, x, y: (x * y.exp()).exp(), lambda g, x, y: x.sqrt().exp(),
+              lambda g, x, y: (1.0 / x - 1.0 / y).exp(),
               lambda g, x, y: (-(g.omega * x * x)).exp()):
-        s = src(f)
-        assert "rg_exp(" in s and "rg_exp_np(" not in s
+        assert "rg_exp(" in src(f), src(f)
 
     g = rgb.Graph(2)
     D = g.omega * (-(g.x(0) * g.x(0))).exp()
@@ -386,8 +420,11 @@ def test_exp_sign_proof_respects_signed_zero_divisors():
     """A quotient's sign is claimed only where its divisor cannot be a zero
     of the other sign: -1/sqrt(x0) at x0 = -0 is 1/(-0) negated, +inf, so
     its exponential keeps the overflow clamp and gives +inf (the variant
-    without the clamp would give NaN there).  Divisors that are
-    exponentials, squares or even powers keep the proof."""
+    without the clamp would give NaN there).  A proven sign alone does not
+    select a variant that maps NaN to 0: -x0^2/e^x1 (inf/inf),
+    -x0^2/x1^2 (0/0) and -x0^2 x1^-2 (0 * inf) can be NaN at finite inputs
+    and take the general exponential, as do the quotients by square
+    roots."""
     from paper_2508_15967_amd import raygraph as rgb
 
     def build(expr_of):
@@ -396,12 +433,12 @@ def test_exp_sign_proof_respects_signed_zero_divisors():
 
     for f in (lambda x, y: (-(x * x) / y.exp()).exp(),
               lambda x, y: (-(x * x) / (y * y)).exp(),
-              lambda x, y: (-(x * x) * (y ** -2)).exp()):
-        assert "rg_exp_np(" in build(f).functions()
-    for f in (lambda x, y: (-(1.0 / x.sqrt())).exp(),
+              lambda x, y: (-(x * x) * (y ** -2)).exp(),
+              lambda x, y: (-(1.0 / x.sqrt())).exp(),
               lambda x, y: (-(x * x) / y.sqrt()).exp(),
               lambda x, y: (-(y.sqrt() ** -1)).exp()):
         s = build(f).functions()
+        # (e^x1 itself, of a NaN-free argument, takes rg_exp_nn)
         assert "rg_exp(" in s and "rg_exp_np(" not in s
 
     prog = build(lambda x, y: (-(1.0 / x.sqrt())).exp())
