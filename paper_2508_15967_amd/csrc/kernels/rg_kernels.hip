@@ -149,15 +149,20 @@ __device__ __forceinline__ void rg_rk4_step(const T *y, T om, T t, T dt, const r
     T K[RG_NY], acc[RG_NY], Y[RG_NY];
 #if RG_ROLL
     const T th = t + h2, tf = t + dt;
-    for (int i = 0; i < RG_NY; i++) Y[i] = y[i];
+    for (int i = 0; i < RG_NY; i++) {
+        Y[i] = y[i];
+        acc[i] = T(0.0);
+    }
 #pragma unroll 1
     for (int s = 0; s < 4; s++) {
         rg_rhs(Y, om, s == 0 ? t : (s == 3 ? tf : th), P, K);
         if (s == 3) break;
-        const T c = s == 2 ? dt : h2;
+        // the stage's coefficients depend on s only (scalar selects); acc
+        // starts at 0, so the first stage adds K1 exactly (1 K1 + 0)
+        const T c = s == 2 ? dt : h2, w = s == 0 ? T(1.0) : T(2.0);
         for (int i = 0; i < RG_NY; i++)
             if (!RG_ZERO(i)) {
-                acc[i] = s == 0 ? K[i] : fma(T(2.0), K[i], acc[i]);
+                acc[i] = fma(w, K[i], acc[i]);
                 Y[i] = fma(c, K[i], y[i]);
             }
         if (st)
