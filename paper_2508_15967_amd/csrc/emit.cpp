@@ -141,6 +141,7 @@ struct Emitter {
     void count(int op, int aux = 0) {
         const IssuedWeights &w = issued_weights();
         fl.ops++;
+        if (cur_inv && op != NEG) fl.inv_ops++;
         switch (op) {
         case ADD: case SUB: case MUL: tally(1, 1); break;
         case DIV: tally(1, w.div); break;
@@ -158,7 +159,11 @@ struct Emitter {
         default: break;
         }
     }
-    void count_fma(int n = 1) { tally(2 * n, 2 * n); fl.ops += n; }
+    void count_fma(int n = 1) {
+        tally(2 * n, 2 * n);
+        fl.ops += n;
+        if (cur_inv) fl.inv_ops += n;
+    }
     void count_plain(double f) { tally(f, f); }
 
     bool fusable_mul(uint32_t m) const {
@@ -427,7 +432,9 @@ struct Emitter {
         case DIV:
             if (g.is_const(nd.a, 1.0)) {
                 e = fn("rg_rcp") + "(" + B + ")";
-                tally(1, issued_weights().rcp); fl.ops++;
+                tally(1, issued_weights().rcp);
+                fl.ops++;
+                if (cur_inv) fl.inv_ops++;
             } else {
                 e = A + " / " + B;
                 count(DIV);

@@ -23,6 +23,7 @@ struct Flops {
     double alg = 0.0;     // add/sub/mul/div/sqrt/exp/... = 1, fma = 2
     double issued = 0.0;  // FP64 add/mul/fma flops of the gfx950 expansion
     uint32_t ops = 0;     // emitted operations (ray-invariant ones included)
+    uint32_t inv_ops = 0; // the ray-invariant ones among them
     double inv_alg = 0.0, inv_issued = 0.0;  // ray-invariant part, not in alg/issued
 };
 

@@ -615,6 +615,155 @@ std::vector<uint32_t> Graph::factor_products(const std::vector<uint32_t> &roots,
     return out;
 }
 
+std::vector<uint32_t> Graph::collect_factors(const std::vector<uint32_t> &roots) {
+    const std::vector<uint32_t> order = reachable(roots);
+    const size_t N0 = nodes_.size();
+    auto is_sum = [&](uint32_t n) {
+        const Node &d = nodes_[n];
+        return d.op == ADD || d.op == SUB ||
+               (d.op == NEG && (nodes_[d.a].op == ADD || nodes_[d.a].op == SUB));
+    };
+    std::vector<char> top(N0, 0);
+    for (uint32_t r : roots)
+        if (r != NONE) top[r] = 1;
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM || is_sum(n)) continue;
+        if (d.a != NONE) top[d.a] = 1;
+        if (d.b != NONE) top[d.b] = 1;
+    }
+    const size_t kMaxTerms = 4096, kMaxFactors = 32;
+    struct Term {
+        std::vector<uint32_t> f;  // factors, sorted (new nodes)
+        int sg;
+    };
+    // factors of a (new) node through products and negations
+    auto factors = [&](uint32_t t, Term &out) {
+        std::vector<uint32_t> stack{t};
+        while (!stack.empty()) {
+            const uint32_t m = stack.back();
+            stack.pop_back();
+            const Node &d = nodes_[m];
+            if (d.op == MUL && out.f.size() + stack.size() < kMaxFactors) {
+                stack.push_back(d.b);
+                stack.push_back(d.a);
+            } else if (d.op == NEG) {
+                out.sg = -out.sg;
+                stack.push_back(d.a);
+            } else {
+                out.f.push_back(m);
+            }
+        }
+        std::sort(out.f.begin(), out.f.end());
+    };
+    auto product = [&](const std::vector<uint32_t> &f) {
+        uint32_t p = NONE;
+        for (uint32_t x : f) p = p == NONE ? x : mul(p, x);
+        return p == NONE ? constant(1.0) : p;
+    };
+    // sum of terms with common factors taken out; terms in a fixed order
+    std::function<uint32_t(std::vector<Term>)> build = [&](std::vector<Term> ts) -> uint32_t {
+        for (;;) {
+            std::map<uint32_t, int> count;
+            for (const Term &t : ts) {
+                for (size_t i = 0; i < t.f.size(); i++)
+                    if (i == 0 || t.f[i] != t.f[i - 1]) count[t.f[i]]++;
+            }
+            uint32_t best = NONE;
+            int bc = 1;
+            for (const auto &kv : count)
+                if (kv.second > bc) {
+                    bc = kv.second;
+                    best = kv.first;
+                }
+            if (best == NONE) break;
+            std::vector<Term> in, rest;
+            for (Term &t : ts) {
+                auto it = std::find(t.f.begin(), t.f.end(), best);
+                if (it == t.f.end()) {
+                    rest.push_back(std::move(t));
+                } else {
+                    t.f.erase(it);
+                    in.push_back(std::move(t));
+                }
+            }
+            const uint32_t inner = build(std::move(in));
+            Term nt{{best, inner}, 1};
+            if (nodes_[inner].op == NEG) {
+                nt.f[1] = nodes_[inner].a;
+                nt.sg = -1;
+            }
+            std::sort(nt.f.begin(), nt.f.end());
+            rest.push_back(std::move(nt));
+            ts = std::move(rest);
+        }
+        // canonical order: by factor lists
+        std::sort(ts.begin(), ts.end(), [](const Term &a, const Term &b) {
+            return a.f != b.f ? a.f < b.f : a.sg < b.sg;
+        });
+        uint32_t acc = NONE;
+        for (const Term &t : ts) {
+            const uint32_t p = product(t.f);
+            if (acc == NONE) acc = t.sg < 0 ? neg(p) : p;
+            else acc = t.sg < 0 ? sub(acc, p) : add(acc, p);
+        }
+        return acc == NONE ? constant(0.0) : acc;
+    };
+    std::vector<uint32_t> nw(N0, NONE);
+    for (uint32_t n : order) {
+        const Node d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM) {
+            nw[n] = n;
+            continue;
+        }
+        if (is_sum(n)) {
+            if (!top[n]) continue;  // folded into its consumers
+            std::vector<Term> ts;
+            double c = 0.0;
+            std::vector<std::pair<uint32_t, int>> stack{{n, 1}};
+            bool too_big = false;
+            while (!stack.empty()) {
+                const auto [m, sg] = stack.back();
+                stack.pop_back();
+                const Node &md = nodes_[m];
+                if (md.op == ADD || md.op == SUB) {
+                    stack.push_back({md.b, md.op == SUB ? -sg : sg});
+                    stack.push_back({md.a, sg});
+                } else if (md.op == NEG && is_sum(m)) {
+                    stack.push_back({md.a, -sg});
+                } else if (md.op == CONST) {
+                    c += sg * md.val;
+                } else {
+                    Term t{{}, sg};
+                    factors(nw[m], t);
+                    ts.push_back(std::move(t));
+                    if (ts.size() > kMaxTerms) {
+                        too_big = true;
+                        break;
+                    }
+                }
+            }
+            if (too_big) return roots;  // leave such graphs alone
+            uint32_t r = build(std::move(ts));
+            if (c != 0.0) r = add(constant(c), r);
+            nw[n] = r;
+            continue;
+        }
+        const uint32_t a = d.a != NONE ? nw[d.a] : NONE, b = d.b != NONE ? nw[d.b] : NONE;
+        switch (d.op) {
+        case MUL: nw[n] = mul(a, b); break;
+        case DIV: nw[n] = div(a, b); break;
+        case NEG: nw[n] = neg(a); break;
+        case POWI: nw[n] = powi(a, d.aux); break;
+        case SPLINE: nw[n] = spline((uint32_t)d.val, d.aux / 4, d.aux % 4, a, b); break;
+        default: nw[n] = unary(d.op, a); break;
+        }
+    }
+    std::vector<uint32_t> out;
+    for (uint32_t r : roots) out.push_back(r == NONE ? NONE : nw[r]);
+    return out;
+}
+
 std::vector<uint32_t> Graph::factor_sums(const std::vector<uint32_t> &roots) {
     const std::vector<uint32_t> order = reachable(roots);
     const size_t N0 = nodes_.size();

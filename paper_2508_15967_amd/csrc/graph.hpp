@@ -101,6 +101,17 @@ public:
     // x + x reduces to 2x).
     std::vector<uint32_t> factor_sums(const std::vector<uint32_t> &roots);
 
+    // Common factors out of sums: every maximal sum is flattened into
+    // signed terms, each term into its factors (through products and
+    // negations), and the factor found in most terms (two at least) is
+    // taken out of those terms, f a + f b -> f (a + b), recursively inside
+    // the new sub-sum and repeatedly over the remaining terms.  Sub-sums are
+    // built with their terms in a fixed order, so a sub-sum that several
+    // sums share under different factors (a directional derivative that the
+    // reverse sweep spreads over several adjoints, say) becomes one node.
+    // Returns the roots' new nodes; reassociation changes rounding only.
+    std::vector<uint32_t> collect_factors(const std::vector<uint32_t> &roots);
+
     // A division whose denominator is invariant along a ray (built from
     // omega, parameters and constants only) and whose numerator is not
     // becomes a product with the reciprocal, which the compiler then

@@ -104,7 +104,7 @@ static void code_cache_put(uint64_t key, const std::vector<char> &code) {
 // that they are computed once per ray; each such value then stays live in
 // registers across the time loop, which the rolled programs (register
 // bound already) do not afford.
-static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist) {
+static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vector<int> &table_slot) {
     // (the state components fixed along a ray are not used for factoring:
     // grouping products around them measured slower on the cold-plasma
     // medium, 558 against 498 VALU instructions per step, with more values
@@ -117,14 +117,33 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist) {
         roots.push_back(s.seed);
         roots.push_back(s.spline_node);
     }
-    const std::vector<uint32_t> nr =
-        g.factor_products(g.factor_sums(g.hoist_divisions(roots, hoist, inv_state)), hoist, inv_state);
-    size_t k = 0;
-    for (Output &o : spec.outputs) o.node = nr[k++];
-    for (SplineSeed &s : spec.spline_seeds) {
-        s.seed = nr[k++];
-        s.spline_node = nr[k++];
-    }
+    auto factored = [&](bool collect) {
+        std::vector<uint32_t> r = g.hoist_divisions(roots, hoist, inv_state);
+        if (collect) r = g.collect_factors(r);
+        const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(r), hoist, inv_state);
+        FunctionSpec out = spec;
+        size_t k = 0;
+        for (Output &o : out.outputs) o.node = nr[k++];
+        for (SplineSeed &s : out.spline_seeds) {
+            s.seed = nr[k++];
+            s.spline_node = nr[k++];
+        }
+        return out;
+    };
+    // Common factors are taken out of sums (Graph::collect_factors) only
+    // where that lowers the emitted operations per evaluation (an fma
+    // counting one; the ray-invariant ones only where they are not
+    // hoisted): it shares the directional derivatives of the cold-plasma
+    // right-hand side and of the anisotropic VJP, but undoes sharing in the
+    // anisotropic right-hand side.
+    FunctionSpec plain = factored(false), coll = factored(true);
+    auto cost = [&](FunctionSpec s) {
+        s.const_table = nullptr;  // counting only: leave the constant table alone
+        Flops f;
+        emit_function(g, s, table_slot, &f);
+        return (long)f.ops - (hoist ? (long)f.inv_ops : 0L);
+    };
+    spec = cost(coll) < cost(plain) ? coll : plain;
 }
 
 rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_program *p) {
@@ -222,7 +241,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         // the integrators keep components with a zero right-hand side fixed,
         // so what depends only on them and on omega is invariant along a ray
         spec.inv_state = zero_mask;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, table_slot);
         fs << emit_function(g, spec, table_slot, &fl_rhs);
         // the Dormand-Prince attempt updates every component: counted with
         // only omega, parameters and constants as invariant
@@ -243,7 +262,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         spec.inv_state = zero_mask;
         Flops fl32;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, table_slot);
         fs << emit_function(g, spec, table_slot, &fl32);
         p->has_f32 = true;
     }
@@ -256,7 +275,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
         spec.returns_value = true;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, table_slot);
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
     {
@@ -271,7 +290,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < d; i++)
             spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
         Flops fl_dk;
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, table_slot);
         fs << emit_function(g, spec, table_slot, &fl_dk);
     }
     p->info.n_nodes_rhs = fl_rhs.ops;
@@ -309,10 +328,10 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         // same state as one function: the work the two share counts once
         FunctionSpec both = spec;
         for (uint32_t i = 0; i < ny; i++) both.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
-        factor_spec(g, spec, !p->rolled);
+        factor_spec(g, spec, !p->rolled, table_slot);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
-        factor_spec(g, both, !p->rolled);
+        factor_spec(g, both, !p->rolled, table_slot);
         emit_function(g, both, table_slot, &fl_rhs_vjp);
     }
     if (!ktab.empty()) {
