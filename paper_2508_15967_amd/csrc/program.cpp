@@ -117,6 +117,7 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vec
         roots.push_back(s.seed);
         roots.push_back(s.spline_node);
     }
+    // the roots with their common factors out of sums, or not
     auto factored = [&](bool collect) {
         std::vector<uint32_t> r = g.hoist_divisions(roots, hoist, inv_state);
         if (collect) r = g.collect_factors(r);
@@ -133,16 +134,18 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vec
     // Common factors are taken out of sums (Graph::collect_factors) only
     // where that lowers the emitted operations per evaluation (an fma
     // counting one; the ray-invariant ones only where they are not
-    // hoisted): it shares the directional derivatives of the cold-plasma
-    // right-hand side and of the anisotropic VJP, but undoes sharing in the
-    // anisotropic right-hand side.
-    FunctionSpec plain = factored(false), coll = factored(true);
+    // hoisted).  It shares the directional derivatives of the cold-plasma
+    // right-hand side and of the anisotropic VJP, but would undo the
+    // sharing of M k between the anisotropic right-hand side's dx/dt and
+    // dk/dt (taking out only factors common to all terms of a sum, or
+    // choosing output by output, found nothing better there).
     auto cost = [&](FunctionSpec s) {
         s.const_table = nullptr;  // counting only: leave the constant table alone
         Flops f;
         emit_function(g, s, table_slot, &f);
         return (long)f.ops - (hoist ? (long)f.inv_ops : 0L);
     };
+    FunctionSpec plain = factored(false), coll = factored(true);
     spec = cost(coll) < cost(plain) ? coll : plain;
 }
 
