@@ -764,6 +764,97 @@ std::vector<uint32_t> Graph::collect_factors(const std::vector<uint32_t> &roots)
     return out;
 }
 
+std::vector<uint32_t> Graph::share_scaled_sums(const std::vector<uint32_t> &roots) {
+    const std::vector<uint32_t> order = reachable(roots);
+    const size_t N0 = nodes_.size();
+    auto is_sum = [&](uint32_t n) { return nodes_[n].op == ADD || nodes_[n].op == SUB; };
+    std::vector<char> top(N0, 0);
+    for (uint32_t r : roots)
+        if (r != NONE) top[r] = 1;
+    for (uint32_t n : order) {
+        const Node &d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM || is_sum(n)) continue;
+        if (d.a != NONE) top[d.a] = 1;
+        if (d.b != NONE) top[d.b] = 1;
+    }
+    // key: the terms (value, coefficient) sorted by value, every
+    // coefficient divided by the power of two of the first one; entry: the
+    // first sum with that key and its power of two
+    std::map<std::vector<std::pair<uint32_t, double>>, std::pair<uint32_t, int>> seen;
+    std::vector<uint32_t> nw(N0, NONE);
+    for (uint32_t n : order) {
+        const Node d = nodes_[n];
+        if (d.op == CONST || d.op == VAR || d.op == PARAM) {
+            nw[n] = n;
+            continue;
+        }
+        const uint32_t a = d.a != NONE ? nw[d.a] : NONE, b = d.b != NONE ? nw[d.b] : NONE;
+        uint32_t r;
+        switch (d.op) {
+        case ADD: r = add(a, b); break;
+        case SUB: r = sub(a, b); break;
+        case MUL: r = mul(a, b); break;
+        case DIV: r = div(a, b); break;
+        case NEG: r = neg(a); break;
+        case POWI: r = powi(a, d.aux); break;
+        case SPLINE: r = spline((uint32_t)d.val, d.aux / 4, d.aux % 4, a, b); break;
+        default: r = unary(d.op, a); break;
+        }
+        nw[n] = r;
+        if (!is_sum(n) || !top[n] || !is_sum(r)) continue;
+        // the terms of the rebuilt maximal sum
+        std::vector<std::pair<uint32_t, double>> terms;
+        bool linear = true;
+        std::vector<std::pair<uint32_t, double>> stack{{r, 1.0}};
+        while (!stack.empty() && linear) {
+            const auto [m, sg] = stack.back();
+            stack.pop_back();
+            const Node &md = nodes_[m];
+            if (md.op == ADD || md.op == SUB) {
+                stack.push_back({md.b, md.op == SUB ? -sg : sg});
+                stack.push_back({md.a, sg});
+            } else if (md.op == NEG) {
+                stack.push_back({md.a, -sg});
+            } else if (md.op == MUL && is_const(md.a) && !is_const(md.b)) {
+                terms.push_back({md.b, sg * nodes_[md.a].val});
+            } else if (md.op == CONST) {
+                linear = false;  // constant terms: not handled
+            } else {
+                terms.push_back({m, sg});
+            }
+        }
+        if (!linear || terms.size() < 2) continue;
+        std::sort(terms.begin(), terms.end());
+        if (!std::isfinite(terms[0].second) || terms[0].second == 0.0) continue;
+        const int e = std::ilogb(terms[0].second);
+        std::vector<std::pair<uint32_t, double>> key;
+        for (const auto &t : terms) {
+            if (!std::isfinite(t.second) || t.second == 0.0) {
+                key.clear();
+                break;
+            }
+            key.push_back({t.first, std::ldexp(t.second, -e)});
+            // the scaled coefficient must be exact
+            if (std::ldexp(key.back().second, e) != t.second) {
+                key.clear();
+                break;
+            }
+        }
+        if (key.empty()) continue;
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            seen[key] = {r, e};
+        } else if (it->second.second != e) {
+            nw[n] = mul(constant(std::ldexp(1.0, e - it->second.second)), it->second.first);
+        } else {
+            nw[n] = it->second.first;
+        }
+    }
+    std::vector<uint32_t> out;
+    for (uint32_t x : roots) out.push_back(x == NONE ? NONE : nw[x]);
+    return out;
+}
+
 std::vector<uint32_t> Graph::factor_sums(const std::vector<uint32_t> &roots) {
     const std::vector<uint32_t> order = reachable(roots);
     const size_t N0 = nodes_.size();

@@ -112,6 +112,13 @@ public:
     // Returns the roots' new nodes; reassociation changes rounding only.
     std::vector<uint32_t> collect_factors(const std::vector<uint32_t> &roots);
 
+    // A sum whose terms are constants times values (or plain values) and
+    // that equals an earlier such sum with every coefficient scaled by one
+    // power of two (2 M k next to M k, from differentiating k.M k) becomes
+    // that sum times the power of two: the same double, one multiplication
+    // instead of the sum.  Returns the roots' new nodes.
+    std::vector<uint32_t> share_scaled_sums(const std::vector<uint32_t> &roots);
+
     // A division whose denominator is invariant along a ray (built from
     // omega, parameters and constants only) and whose numerator is not
     // becomes a product with the reciprocal, which the compiler then

@@ -121,7 +121,8 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vec
     auto factored = [&](bool collect) {
         std::vector<uint32_t> r = g.hoist_divisions(roots, hoist, inv_state);
         if (collect) r = g.collect_factors(r);
-        const std::vector<uint32_t> nr = g.factor_products(g.factor_sums(r), hoist, inv_state);
+        const std::vector<uint32_t> nr =
+            g.share_scaled_sums(g.factor_products(g.factor_sums(r), hoist, inv_state));
         FunctionSpec out = spec;
         size_t k = 0;
         for (Output &o : out.outputs) o.node = nr[k++];
