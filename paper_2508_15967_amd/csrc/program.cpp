@@ -11,6 +11,7 @@
 #include <hip/hiprtc.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstdlib>
 
 #include <chrono>
@@ -104,7 +105,8 @@ static void code_cache_put(uint64_t key, const std::vector<char> &code) {
 // that they are computed once per ray; each such value then stays live in
 // registers across the time loop, which the rolled programs (register
 // bound already) do not afford.
-static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vector<int> &table_slot) {
+static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vector<int> &table_slot,
+                        bool collect_ok) {
     // (the state components fixed along a ray are not used for factoring:
     // grouping products around them measured slower on the cold-plasma
     // medium, 558 against 498 VALU instructions per step, with more values
@@ -117,12 +119,15 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vec
         roots.push_back(s.seed);
         roots.push_back(s.spline_node);
     }
-    // the roots with their common factors out of sums, or not
-    auto factored = [&](bool collect) {
-        std::vector<uint32_t> r = g.hoist_divisions(roots, hoist, inv_state);
-        if (collect) r = g.collect_factors(r);
-        const std::vector<uint32_t> nr =
-            g.share_scaled_sums(g.factor_products(g.factor_sums(r), hoist, inv_state));
+    // the roots factored, with common factors taken out of sums in
+    // `rounds` rounds (a second round finds the factors that the sharing of
+    // scaled sums exposes: 2 x a + 2 y b -> 2 (x a + y b))
+    auto factored = [&](int rounds) {
+        std::vector<uint32_t> nr = g.hoist_divisions(roots, hoist, inv_state);
+        for (int i = 0; i < std::max(rounds, 1); i++) {
+            if (rounds > 0) nr = g.collect_factors(nr);
+            nr = g.share_scaled_sums(g.factor_products(g.factor_sums(nr), hoist, inv_state));
+        }
         FunctionSpec out = spec;
         size_t k = 0;
         for (Output &o : out.outputs) o.node = nr[k++];
@@ -135,19 +140,28 @@ static void factor_spec(Graph &g, FunctionSpec &spec, bool hoist, const std::vec
     // Common factors are taken out of sums (Graph::collect_factors) only
     // where that lowers the emitted operations per evaluation (an fma
     // counting one; the ray-invariant ones only where they are not
-    // hoisted).  It shares the directional derivatives of the cold-plasma
-    // right-hand side and of the anisotropic VJP, but would undo the
-    // sharing of M k between the anisotropic right-hand side's dx/dt and
-    // dk/dt (taking out only factors common to all terms of a sum, or
-    // choosing output by output, found nothing better there).
+    // hoisted), in one round or two.  It shares the directional
+    // derivatives of the cold-plasma right-hand side and of the anisotropic
+    // VJP.  Not for the right-hand sides of rolled programs (collect_ok
+    // false): for the anisotropic medium two rounds save 15 of 491
+    // operations but turn M_b k into nine sums over the blobs, and the
+    // forward kernel then needs 204 VGPRs (two waves per SIMD) against 119.
     auto cost = [&](FunctionSpec s) {
         s.const_table = nullptr;  // counting only: leave the constant table alone
         Flops f;
         emit_function(g, s, table_slot, &f);
         return (long)f.ops - (hoist ? (long)f.inv_ops : 0L);
     };
-    FunctionSpec plain = factored(false), coll = factored(true);
-    spec = cost(coll) < cost(plain) ? coll : plain;
+    spec = factored(0);
+    long best = cost(spec);
+    for (int rounds = 1; rounds <= (collect_ok ? 2 : 0); rounds++) {
+        FunctionSpec c = factored(rounds);
+        const long k = cost(c);
+        if (k < best) {
+            best = k;
+            spec = c;
+        }
+    }
 }
 
 rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_program *p) {
@@ -245,7 +259,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         // the integrators keep components with a zero right-hand side fixed,
         // so what depends only on them and on omega is invariant along a ray
         spec.inv_state = zero_mask;
-        factor_spec(g, spec, !p->rolled, table_slot);
+        factor_spec(g, spec, !p->rolled, table_slot, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_rhs);
         // the Dormand-Prince attempt updates every component: counted with
         // only omega, parameters and constants as invariant
@@ -266,7 +280,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < ny; i++) spec.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
         spec.inv_state = zero_mask;
         Flops fl32;
-        factor_spec(g, spec, !p->rolled, table_slot);
+        factor_spec(g, spec, !p->rolled, table_slot, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl32);
         p->has_f32 = true;
     }
@@ -279,7 +293,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
             "const rg_P &P) {\n  (void)om; (void)t; (void)P; (void)y;";
         spec.outputs.push_back({D, "", false});
         spec.returns_value = true;
-        factor_spec(g, spec, !p->rolled, table_slot);
+        factor_spec(g, spec, !p->rolled, table_slot, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_D);
     }
     {
@@ -294,7 +308,7 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         for (uint32_t i = 0; i < d; i++)
             spec.outputs.push_back({g.df(D, yv[d + i]), "out[" + std::to_string(i + 1) + "]", false});
         Flops fl_dk;
-        factor_spec(g, spec, !p->rolled, table_slot);
+        factor_spec(g, spec, !p->rolled, table_slot, !p->rolled);
         fs << emit_function(g, spec, table_slot, &fl_dk);
     }
     p->info.n_nodes_rhs = fl_rhs.ops;
@@ -332,10 +346,10 @@ rg_status build_program(Graph &g, uint32_t D, const rg_compile_opts &opts, rg_pr
         // same state as one function: the work the two share counts once
         FunctionSpec both = spec;
         for (uint32_t i = 0; i < ny; i++) both.outputs.push_back({f[i], "f[" + std::to_string(i) + "]", false});
-        factor_spec(g, spec, !p->rolled, table_slot);
+        factor_spec(g, spec, !p->rolled, table_slot, true);
         fs << emit_function(g, spec, table_slot, &fl_vjp);
         p->info.n_nodes_vjp = fl_vjp.ops;
-        factor_spec(g, both, !p->rolled, table_slot);
+        factor_spec(g, both, !p->rolled, table_slot, true);
         emit_function(g, both, table_slot, &fl_rhs_vjp);
     }
     if (!ktab.empty()) {
