@@ -455,3 +455,23 @@ def test_exp_sign_proof_respects_signed_zero_divisors():
                       C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
     assert Dv[0] == np.inf and Dv[1] == 0.0, Dv
     assert abs(Dv[2] - np.exp(-0.5)) <= 2e-16 * np.exp(-0.5)
+
+
+def test_emitted_operation_counts():
+    """Guard on the emitter's output size (host compile only, no GPU): the
+    per-evaluation flops of the compiled graph for the anisotropic medium
+    (right-hand side and VJP; the VJP relies on the common-factor and
+    scaled-sum passes sharing (x - c_b).v and M_b k) and for the cold-plasma
+    right-hand side (common factors of its determinant), with the flops of
+    one adjoint step that the benchmark's roofline counts."""
+    from paper_2508_15967_amd import media
+    w = W.make("5", 16)
+    g, D, _ = media.build(w.medium)
+    info = g.compile(D, want_adjoint=True, compile_only=True).info()
+    assert info["rhs_flops_alg"] <= 742, info
+    assert info["vjp_flops_alg"] <= 1467, info
+    assert info["adj_step_flops_alg"] <= 8987, info
+    cp = COLD["cO2"]()
+    g, D, _ = media.build(cp.medium)
+    info = g.compile(D, compile_only=True).info()
+    assert info["rhs_flops_alg"] <= 114, info
