@@ -336,7 +336,9 @@ typedef struct {
     double *dL_dx0;             /* [dim][n], nullable */
     double *dL_dk0;             /* [dim][n], nullable */
     double *const *dL_dparams;  /* host array of n_params device pointers (entries
-                                   nullable); overwritten, not accumulated */
+                                   nullable); overwritten, not accumulated.
+                                   The gradient buffers may overlap no other
+                                   buffer of the call (RG_EINVAL) */
     /* per-call device scratch owned by the caller: at least the bytes
        rg_adjoint_workspace_size reports (the segment buffer of stage states
        and the per-workgroup gradient partials; with fwd->checkpoints NULL

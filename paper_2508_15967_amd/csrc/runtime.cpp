@@ -938,22 +938,44 @@ static rg_status adjoint_impl(rg_program *p, const rg_adjoint_desc &ad, hipStrea
     if (ad.dL_dk_end) RGCHK(check_dev(ad.dL_dk_end, 8 * dim * n, "dL_dk_end"));
     if (ad.dL_dx0) RGCHK(check_dev(ad.dL_dx0, 8 * dim * n, "dL_dx0"));
     if (ad.dL_dk0) RGCHK(check_dev(ad.dL_dk0, 8 * dim * n, "dL_dk0"));
-    // the workspace is written before the seeds are read
-    {
-        const char *w0 = (const char *)ad.workspace;
-        const std::pair<const void *, size_t> bufs[] = {{ad.dL_dx_end, 8 * dim * n}, {ad.dL_dk_end, 8 * dim * n},
-                                                        {ad.dL_dx0, 8 * dim * n}, {ad.dL_dk0, 8 * dim * n}};
-        for (const auto &b : bufs) {
-            const char *b0 = (const char *)b.first;
-            if (b0 && need && w0 < b0 + b.second && b0 < w0 + need)
-                return fail(RG_EINVAL, "workspace overlaps an adjoint seed or gradient buffer");
-        }
-    }
     for (uint32_t i = 0; i < p->n_params; i++)
         if (ad.dL_dparams && ad.dL_dparams[i]) {
             RGCHK(check_dev(ad.dL_dparams[i], 8 * (size_t)p->param_len[i], "dL_dparams[i]"));
             a.dparams[i] = ad.dL_dparams[i];
         }
+    // What the call writes (the gradients, the workspace) may overlap
+    // nothing it reads and nothing else it writes: the parameter gradients
+    // are zeroed and the workspace filled before the seeds, checkpoints and
+    // parameters are read.
+    {
+        struct Buf { const void *p; size_t bytes; std::string name; };
+        std::vector<Buf> rd = {{d.x0, 8 * dim * n, "x0"}, {d.k0, 8 * dim * n, "k0"}, {d.omega, 8 * n, "omega"},
+                               {d.t0, 8 * n, "t0"}, {ad.dL_dx_end, 8 * dim * n, "dL_dx_end"},
+                               {ad.dL_dk_end, 8 * dim * n, "dL_dk_end"}};
+        if (d.checkpoints) {
+            const size_t nc = ((size_t)d.n_steps + d.checkpoint_every - 1) / d.checkpoint_every;
+            rd.push_back({d.checkpoints, 8 * nc * (2 * dim + 1) * n, "checkpoints"});
+            rd.push_back({d.steps_out, 4 * n, "steps_out"});
+        }
+        std::vector<Buf> wr = {{ad.dL_dx0, 8 * dim * n, "dL_dx0"}, {ad.dL_dk0, 8 * dim * n, "dL_dk0"},
+                               {ad.workspace, need, "workspace"}};
+        for (uint32_t i = 0; i < p->n_params; i++) {
+            const std::string k = std::to_string(i);
+            rd.push_back({d.params[i], 8 * (size_t)p->param_len[i], "params[" + k + "]"});
+            wr.push_back({a.dparams[i], 8 * (size_t)p->param_len[i], "dL_dparams[" + k + "]"});
+        }
+        auto overlap = [](const Buf &u, const Buf &v) {
+            if (!u.p || !v.p || !u.bytes || !v.bytes) return false;
+            const char *a0 = (const char *)u.p, *b0 = (const char *)v.p;
+            return a0 < b0 + v.bytes && b0 < a0 + u.bytes;
+        };
+        for (size_t i = 0; i < wr.size(); i++) {
+            for (const Buf &r : rd)
+                if (overlap(wr[i], r)) return fail(RG_EINVAL, wr[i].name + " overlaps " + r.name);
+            for (size_t j = i + 1; j < wr.size(); j++)
+                if (overlap(wr[i], wr[j])) return fail(RG_EINVAL, wr[i].name + " overlaps " + wr[j].name);
+        }
+    }
     a.lam_x = ad.dL_dx_end;
     a.lam_k = ad.dL_dk_end;
     a.gx0 = ad.dL_dx0;

@@ -144,3 +144,29 @@ def test_adjoint_workspace_refused_when_short():
     with pytest.raises(rgb.RayGraphError) as e:
         prog.adjoint_desc(out["_desc"], lx, None, torch.empty_like(x0), None, [], workspace=small)
     assert e.value.status == rgb.RG_EINVAL and "workspace" in str(e.value)
+
+
+def test_adjoint_gradient_buffers_may_not_overlap():
+    """A parameter gradient that shares memory with a parameter it is the
+    gradient of, or with another gradient output, is refused before any
+    launch (it is zeroed before the parameters are read)."""
+    torch = U.torch_mod()
+    w = W.make("4", 256)
+    w.n_steps = 120
+    _, _, prog, params = U.program(w, want_adjoint=True)
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    pt = [U.dev(p) for p in params]
+    out = prog.trace(x0, k0, om, pt, dt=w.dt, n_steps=w.n_steps, checkpoint_every=100)
+    lx = (2.0 * (out["x"] - U.dev(w.targets))).contiguous()
+    big = torch.empty(pt[0].numel() + x0.numel(), dtype=torch.float64, device="cuda")
+    cases = (([pt[0]], torch.empty_like(x0), "overlaps params[0]"),
+             ([big[:pt[0].numel()]], big[:x0.numel()].view(x0.shape), "overlaps dL_dparams[0]"))
+    for gp, gx0, msg in cases:
+        with pytest.raises(rgb.RayGraphError) as e:
+            prog.adjoint_desc(out["_desc"], lx, None, gx0, None, gp)
+        assert e.value.status == rgb.RG_EINVAL and msg in str(e.value), str(e.value)
+    gx0 = torch.empty_like(x0)
+    gp = [torch.empty_like(pt[0])]
+    prog.adjoint_desc(out["_desc"], lx, None, gx0, None, gp)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(gp[0]).all()) and bool(torch.isfinite(gx0).all())
