@@ -131,6 +131,34 @@ def test_empty_and_single_ray(oracle):
     prog.trace_desc(d)  # zero rays is a no-op
 
 
+@pytest.mark.parametrize("mode", [rgb.PERSISTENT, rgb.PLAIN])
+def test_zero_steps(mode):
+    """n_steps = 0, the degenerate trace: the endpoints are the launch
+    states (bitwise), no step is taken, and the adjoint is the identity map
+    (dL/dx0 = dL/dx_end, dL/dk0 = dL/dk_end) with zero parameter
+    gradients."""
+    torch = U.torch_mod()
+    w = W.make("5", 96)
+    w.n_steps = 0
+    print(f"[case] zero steps mode={mode}", flush=True)
+    _, _, prog, params = U.program(w, want_adjoint=True)
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    pt = [U.dev(p) for p in params]
+    out = prog.trace(x0, k0, om, pt, dt=w.dt, n_steps=0, checkpoint_every=10, mode=mode)
+    torch.cuda.synchronize()
+    assert torch.equal(out["x"], x0) and torch.equal(out["k"], k0)
+    assert int(out["steps"].abs().max()) == 0 and int(out["status"].abs().max()) == 0
+    assert float(out["t"].abs().max()) == 0.0
+    lx = (2.0 * (out["x"] - U.dev(w.targets))).contiguous()
+    lk = torch.ones_like(k0)
+    gx0, gk0 = torch.empty_like(x0), torch.empty_like(k0)
+    gp = [torch.full_like(p, 5.0) for p in pt]
+    prog.adjoint_desc(out["_desc"], lx, lk, gx0, gk0, gp)
+    torch.cuda.synchronize()
+    assert torch.equal(gx0, lx) and torch.equal(gk0, lk)
+    assert all(float(g.abs().max()) == 0.0 for g in gp)
+
+
 def test_boundary_rejects_bad_buffers():
     """Host pointers, undersized device buffers and overlapping outputs are
     refused before any launch (RG_EINVAL), with a message."""
