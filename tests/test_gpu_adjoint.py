@@ -96,14 +96,14 @@ def test_adjoint_independent_of_checkpoint_interval(cfg, n):
     """The reverse sweep recomputes each segment from its checkpoint with
     the forward's own step arithmetic, so where the checkpoints fall does
     not change the per-ray results: endpoints and dL/dx0, dL/dk0 bitwise
-    equal for intervals 1, 7 (a ragged last segment), 10 and the whole
-    trace; the parameter gradients, summed over rays through atomics, equal
-    to rounding."""
+    equal for intervals 1, 9 (a ragged last segment), 10, the whole trace
+    and one longer than the trace (a single, short segment); the parameter
+    gradients, summed over rays through atomics, equal to rounding."""
     w = W.make(cfg, n)
     w.n_steps = 700
     print(f"[case] checkpoint intervals cfg={cfg} n={n}", flush=True)
     ref = _gpu_grad(w, ckpt=10)
-    for ce in (1, 7, 700):
+    for ce in (1, 9, 700, 1000):
         g = _gpu_grad(w, ckpt=ce)
         assert np.array_equal(g["x"], ref["x"]), ce
         assert np.array_equal(g["gx0"], ref["gx0"]) and np.array_equal(g["gk0"], ref["gk0"]), ce
