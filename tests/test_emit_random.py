@@ -1,0 +1,110 @@
+"""The emission pipeline on random dispersion relations (no GPU, no
+oracle): the right-hand side f = (-D_k/D_w, D_x/D_w), D and the
+vector-Jacobian product v^T df/dy of the emitted device functions, compiled
+as host C++, against the graph front end's own evaluation of the same
+symbolic derivatives taken on the unfactored graph.  The random relations
+are sums of products over a pool that shares sub-sums, scaled copies of
+sums, Gaussians and ray invariants (omega, parameter elements), so that the
+common-factor, scaled-sum, product and division passes all rewrite them;
+a pass that drops a term, flips a sign or mixes up an operand changes the
+values far beyond rounding.  The larger relations carry enough constants
+for the rolled form with its constant table."""
+import ctypes as C
+import re
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2508_15967_amd import raygraph as rgb
+from tests.test_emit_host import _host_lib
+
+
+def _random_D(g, rng, n_terms):
+    x = [g.x(i) for i in range(3)]
+    k = [g.k(i) for i in range(3)]
+    om = g.omega
+    s = g.param("s", 4)
+    base = x + k
+    sums = []
+    for _ in range(4):
+        i, j = rng.choice(6, 2, replace=False)
+        c1, c2 = rng.choice([-2.0, -1.0, -0.5, 0.5, 1.0, 1.5, 2.0], 2)
+        lin = c1 * base[i] + c2 * base[j]
+        sums.append(lin)
+        sums.append((2.0 * c1) * base[i] + (2.0 * c2) * base[j])  # a scaled copy of the same sum
+        sums.append(lin + float(rng.uniform(-1.0, 1.0)))
+    gauss = []
+    for _ in range(3):
+        i = int(rng.integers(0, 3))
+        c, w = float(rng.uniform(-1.0, 1.0)), float(rng.uniform(1.0, 2.0))
+        d = x[i] - c
+        gauss.append((d * d * (-1.0 / (w * w))).exp())
+    inv = [g.elem(s, j) for j in range(4)] + [om]
+    pool = base + sums + gauss
+    D = k[0] * k[0] + k[1] * k[1] + k[2] * k[2] - om * om
+    for _ in range(n_terms):
+        nf = int(rng.integers(2, 4))
+        fs = [pool[int(rng.integers(0, len(pool)))] for _ in range(nf)]
+        if rng.random() < 0.5:
+            fs.append(inv[int(rng.integers(0, 4))])  # a parameter element
+        if rng.random() < 0.1:
+            fs.append(om)
+        t = fs[0]
+        for f in fs[1:]:
+            t = t * f
+        D = D + float(rng.uniform(0.02, 0.1)) * float(rng.choice([-1.0, 1.0])) * t
+    return D, x, k, om
+
+
+@pytest.mark.parametrize("seed,n_terms", [(0, 6), (1, 10), (2, 14), (3, 40), (4, 60), (5, 8), (6, 12), (7, 20)])
+def test_emitted_functions_match_graph(seed, n_terms):
+    rng = np.random.default_rng(seed)
+    g = rgb.Graph(3)
+    D, x, k, om = _random_D(g, rng, n_terms)
+    Dw = D.df(om)
+    f_nodes = [-(D.df(ki)) / Dw for ki in k] + [D.df(xi) / Dw for xi in x]
+    ys = x + k
+    J_nodes = [[fi.df(yj) for yj in ys] for fi in f_nodes]
+    prog = g.compile(D, want_adjoint=True, compile_only=True)
+    # parameter-gradient slots: slot e holds element rg_grad_elem[e] of the
+    # (only) parameter array
+    src = prog.source()
+    ns = int(prog.info()["n_grad_slots"])
+    slots = [int(t) for t in re.search(r"rg_grad_elem\[\d+\] = \{([^}]*)\}", src).group(1).split(",")][:ns]
+    assert re.search(r"rg_grad_param\[\d+\] = \{([^}]*)\}", src).group(1).replace(" ", "").strip("0,") == ""
+    assert ns == len(set(slots))
+    P_nodes = [[fi.df(g.elem(0, j)) for j in slots] for fi in f_nodes]
+    params = [np.ascontiguousarray(rng.uniform(0.5, 1.5, 4))]
+    n = 64
+    y = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (3, n)), rng.uniform(0.5, 1.5, (3, n))]))
+    omv = np.full(n, 1.5)
+    v = np.ascontiguousarray(rng.standard_normal((6, n)))
+    f_ref = np.zeros((6, n))
+    D_ref = np.zeros(n)
+    jv_ref = np.zeros((6, n))
+    gp_ref = np.zeros(len(slots))
+    for r in range(n):
+        xv, kv = list(y[:3, r]), list(y[3:, r])
+        ev = lambda nd: g.eval(nd, xv, kv, 1.5, params=params)
+        D_ref[r] = ev(D)
+        f_ref[:, r] = [ev(fi) for fi in f_nodes]
+        J = np.array([[ev(J_nodes[i][j]) for j in range(6)] for i in range(6)])
+        jv_ref[:, r] = v[:, r] @ J
+        gp_ref += v[:, r] @ np.array([[ev(P_nodes[i][e]) for e in range(len(slots))] for i in range(6)])
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, True, tmp)
+        pp = (C.c_void_p * 8)(params[0].ctypes.data, *([None] * 7))
+        f = np.zeros((6, n))
+        Dv = np.zeros(n)
+        lib.host_eval(n, 6, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
+                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+        jv = np.zeros((6, n))
+        gp = np.zeros(64)
+        lib.host_vjp(n, 6, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
+                     C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
+    assert np.abs(Dv - D_ref).max() <= 1e-13 * (1.0 + np.abs(D_ref).max())
+    assert (np.abs(f - f_ref).max(axis=0) / np.abs(f_ref).max(axis=0)).max() < 1e-12
+    assert (np.abs(jv - jv_ref).max(axis=0) / np.abs(jv_ref).max(axis=0)).max() < 1e-11
+    if slots:
+        assert np.abs(gp[:len(slots)] - gp_ref).max() < 1e-11 * np.abs(gp_ref).max()
