@@ -407,6 +407,11 @@ class Program:
             _check_tensor(p, "param", f64)
         d = TraceDesc()
         d.struct_size = C.sizeof(TraceDesc)
+        # the descriptor holds every tensor it points to, so that a later
+        # call on it (the adjoint reads x0, k0, omega, the parameters, the
+        # checkpoints and the step counts) never sees freed memory
+        d._refs = (x0, k0, omega, t0, budget, traj, traj_D, x_out, k_out, t_out, status_out, steps_out,
+                   checkpoints, attempts_out, tuple(params))
         d.n_rays = int(x0.shape[-1])
         d.x0, d.k0, d.t0, d.omega = _dptr(x0), _dptr(k0), _dptr(t0), _dptr(omega)
         pp = (C.c_void_p * max(1, len(params)))(*[_dptr(p) for p in params])

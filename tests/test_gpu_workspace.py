@@ -170,3 +170,34 @@ def test_adjoint_gradient_buffers_may_not_overlap():
     prog.adjoint_desc(out["_desc"], lx, None, gx0, None, gp)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(gp[0]).all()) and bool(torch.isfinite(gx0).all())
+
+
+def test_descriptor_keeps_its_tensors():
+    """A trace whose inputs were temporaries: the descriptor it returns
+    holds them, so the adjoint on it, after new allocations of the same
+    sizes, reads the launch states and parameters of the trace (bitwise the
+    gradients of a trace whose inputs the caller kept)."""
+    torch = U.torch_mod()
+    w = W.make("5", 256)
+    w.n_steps = 60
+    _, _, prog, params = U.program(w, want_adjoint=True)
+    res = []
+    for keep in (True, False):
+        x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+        pt = [U.dev(p) for p in params]
+        out = prog.trace(x0, k0, om, pt, dt=w.dt, n_steps=w.n_steps, checkpoint_every=10)
+        if not keep:
+            del x0, k0, om, pt
+            # blocks of the same sizes, filled with other values
+            junk = [U.dev(np.full(a.shape, 3.0)) for a in (w.x0, w.k0, w.omega, *params)]
+        lx = (2.0 * (out["x"] - U.dev(w.targets))).contiguous()
+        gx0 = torch.empty((3, w.n), dtype=torch.float64, device="cuda")
+        gk0 = torch.empty_like(gx0)
+        gp = [torch.empty(p.size, dtype=torch.float64, device="cuda") for p in params]
+        prog.adjoint_desc(out["_desc"], lx, None, gx0, gk0, gp)
+        torch.cuda.synchronize()
+        res.append((gx0.cpu().numpy(), gk0.cpu().numpy(), gp[0].cpu().numpy()))
+        if not keep:
+            del junk
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
