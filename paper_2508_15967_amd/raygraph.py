@@ -555,6 +555,8 @@ class Program:
         import torch
         for t, nm in ((x, "x"), (k, "k"), (omega, "omega")):
             _check_tensor(t, nm, torch.float64)
+        for p in params:
+            _check_tensor(p, "param", torch.float64)
         n = int(x.shape[-1])
         dev = x.device
         it = torch.empty(n, dtype=torch.int32, device=dev)
@@ -576,6 +578,9 @@ class Program:
         import torch
         _check_tensor(y, "y", torch.float64)
         _check_tensor(omega, "omega", torch.float64)
+        _check_tensor(t, "t", torch.float64)
+        for p in params:
+            _check_tensor(p, "param", torch.float64)
         n = int(y.shape[-1])
         f = torch.empty_like(y)
         D = torch.empty(n, dtype=torch.float64, device=y.device)
