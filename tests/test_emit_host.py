@@ -475,3 +475,44 @@ def test_emitted_operation_counts():
     g, D, _ = media.build(cp.medium)
     info = g.compile(D, compile_only=True).info()
     assert info["rhs_flops_alg"] <= 114, info
+
+
+def test_non_square_spline_matches_oracle(oracle):
+    """A B-spline medium whose grid and domain are not square (9 x 14
+    coefficients over [-3, 4] x [-5, 2]): the emitted right-hand side, D,
+    VJP and coefficient gradient against the oracle, at points inside the
+    domain and beyond its edges (where the edge cells' cubics extend).  A
+    mix-up of the two axes' sizes or spacings, invisible on the square
+    workload grid, fails it."""
+    from paper_2508_15967_amd import media
+    rng = np.random.default_rng(11)
+    nx, ny = 9, 14
+    coef = 1.0 + 0.05 * rng.standard_normal((nx, ny))
+    med = W.Medium(W.SPLINE2D, 2, coef=coef, lo=np.array([-3.0, -5.0]), hi=np.array([4.0, 2.0]))
+    g, D, params = media.build(med)
+    prog = g.compile(D, want_adjoint=True, compile_only=True)
+    n = 500
+    y = np.ascontiguousarray(np.concatenate([
+        np.stack([rng.uniform(-3.5, 4.5, n), rng.uniform(-5.5, 2.5, n)]),
+        np.stack([rng.uniform(0.5, 1.5, n), rng.uniform(-0.5, 0.5, n)])]))
+    om = np.ascontiguousarray(rng.uniform(0.9, 1.1, n))
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, True, tmp)
+        pp = _ptrs(params)
+        grad = np.zeros(nx * ny)
+        lib.set_table(0, C.c_void_p(params[0].ctypes.data), ny, C.c_void_p(grad.ctypes.data))
+        f, Dv = np.zeros((4, n)), np.zeros(n)
+        lib.host_eval(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
+                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+        v = np.ascontiguousarray(rng.standard_normal((4, n)))
+        jv = np.zeros((4, n))
+        gp = np.zeros(64)
+        lib.host_vjp(n, 4, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
+                     C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
+    fo, Do, J = oracle.eval_points(med, y, om, jac=True)
+    assert (np.abs(f - fo).max(axis=0) / np.abs(fo).max(axis=0)).max() < 1e-13
+    assert np.abs(Dv - Do).max() < 1e-13 * (1 + np.abs(Do).max())
+    jvo = np.einsum("nij,in->jn", J, v)
+    assert np.abs(jv - jvo).max() / np.abs(jvo).max() < 1e-12
+    go = oracle.param_vjp_points(med, y, om, v)
+    assert np.abs(grad - go).max() / np.abs(go).max() < 1e-12

@@ -31,7 +31,8 @@ def _gpu_grad(w, ckpt=100):
     gp = [torch.empty_like(p) for p in pt]
     prog.adjoint_desc(out["_desc"], lx, None, gx0, gk0, gp)
     torch.cuda.synchronize()
-    return {"x": out["x"].cpu().numpy(), "gx0": gx0.cpu().numpy(), "gk0": gk0.cpu().numpy(),
+    return {"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy(), "gx0": gx0.cpu().numpy(),
+            "gk0": gk0.cpu().numpy(),
             "gp": [g.cpu().numpy() for g in gp], "prog": prog, "pt": pt, "in": (x0, k0, om)}
 
 
@@ -325,3 +326,33 @@ def test_deterministic_spline_gradients(oracle):
 def rgb_mode(name):
     from paper_2508_15967_amd import raygraph as rgb
     return getattr(rgb, name)
+
+
+def test_non_square_spline_matches_oracle(oracle):
+    """A B-spline medium whose grid and domain are not square (9 x 14
+    coefficients over [-3, 4] x [-5, 2]; the workload grid is square, so an
+    axis mix-up in the kernels' table staging, gathers or gradient scatter
+    would not show there): 1,024 rays x 500 steps, endpoints per ray and
+    the adjoint (dL/dx0, dL/dk0 per ray, dL/dcoef per element) against the
+    oracle."""
+    rng = np.random.default_rng(12)
+    nx, ny, n = 9, 14, 1024
+    coef = 1.0 + 0.05 * rng.standard_normal((nx, ny))
+    lo, hi = np.array([-3.0, -5.0]), np.array([4.0, 2.0])
+    med = W.Medium(W.SPLINE2D, 2, coef=coef, lo=lo, hi=hi)
+    x0 = np.stack([np.full(n, -2.5), rng.uniform(-4.5, 1.5, n)])
+    k0 = np.stack([np.sqrt(W._spline_N(coef, lo, hi, x0[0], x0[1])), np.zeros(n)])
+    w = W.Workload("spline_non_square", "4", 2, med, x0, k0, np.ones(n), W.RK4, dt=2e-3, n_steps=500,
+                   targets=rng.uniform(-2.0, 3.0, (2, n)), ckpt_every=50)
+    print(f"[case] non-square spline n={n} steps={w.n_steps}", flush=True)
+    g = _gpu_grad(w, ckpt=50)
+    bad, o = U.ill_conditioned(oracle, w)
+    assert bad.mean() <= U.MAX_ILL
+    ex, ek = U.ray_errors(g, o, w.omega, w.dim)
+    assert ex[~bad].max() < U.TOL and ek[~bad].max() < U.TOL, (ex[~bad].max(), ek[~bad].max())
+    lam = np.concatenate([2 * (o["x"] - w.targets), np.zeros_like(o["k"])])
+    lam0, go = oracle.adjoint(w, lam)
+    ok = ~bad
+    assert _ray_rel(g["gx0"], lam0[:2])[ok].max() < ORACLE_TOL
+    assert _ray_rel(g["gk0"], lam0[2:])[ok].max() < ORACLE_TOL
+    assert _elem_rel(g["gp"][0], go).max() < ORACLE_TOL
