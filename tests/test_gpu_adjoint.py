@@ -9,6 +9,7 @@ parameters (spline coefficients / blob scales, summed over rays).
 import numpy as np
 import pytest
 
+from paper_2508_15967_amd import raygraph as rgb
 from paper_2508_15967_amd import workloads as W
 from tests import gpu_util as U
 
@@ -356,3 +357,38 @@ def test_non_square_spline_matches_oracle(oracle):
     assert _ray_rel(g["gx0"], lam0[:2])[ok].max() < ORACLE_TOL
     assert _ray_rel(g["gk0"], lam0[2:])[ok].max() < ORACLE_TOL
     assert _elem_rel(g["gp"][0], go).max() < ORACLE_TOL
+
+
+@pytest.mark.parametrize("mode", [rgb.PERSISTENT, rgb.PLAIN])
+def test_adjoint_of_rays_that_leave_the_box(oracle, mode):
+    """Rays that end early: the spline workload in a box that most rays
+    leave mid-trace, at different steps and inside checkpoint segments.
+    The adjoint runs over each ray's own accepted steps (the loss is on its
+    exit state): statuses and step counts equal to the oracle's, dL/dx0,
+    dL/dk0 per ray and dL/dcoef per element against the oracle's adjoint."""
+    torch = U.torch_mod()
+    w = W.make("4", 1024)
+    w.n_steps = 1000
+    w.box_lo, w.box_hi = np.array([-10.0, -10.0]), np.array([-6.5, 10.0])
+    print(f"[case] adjoint with box exits mode={mode}", flush=True)
+    _, _, prog, params = U.program(w, want_adjoint=True)
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    pt = [U.dev(p) for p in params]
+    out = prog.trace(x0, k0, om, pt, dt=w.dt, n_steps=w.n_steps, checkpoint_every=100, mode=mode,
+                     box=(list(w.box_lo), list(w.box_hi)))
+    torch.cuda.synchronize()
+    o = oracle.trace(w)
+    st, ns = out["status"].cpu().numpy(), out["steps"].cpu().numpy()
+    assert np.array_equal(st, o["status"]) and np.array_equal(ns, o["steps"])
+    exited = st == rgb.RAY_EXITED_BOX
+    assert exited.mean() > 0.5 and len(np.unique(ns[exited])) > 10, (exited.mean(), np.unique(ns))
+    ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()}, o, w.omega, w.dim)
+    assert ex.max() < U.TOL and ek.max() < U.TOL
+    lx = (2.0 * (out["x"] - U.dev(w.targets))).contiguous()
+    gx0, gk0, gp = torch.empty_like(x0), torch.empty_like(k0), [torch.empty_like(p) for p in pt]
+    prog.adjoint_desc(out["_desc"], lx, None, gx0, gk0, gp)
+    torch.cuda.synchronize()
+    lam0, go = oracle.adjoint(w, np.concatenate([2 * (o["x"] - w.targets), np.zeros_like(o["k"])]))
+    assert _ray_rel(gx0.cpu().numpy(), lam0[:2]).max() < ORACLE_TOL
+    assert _ray_rel(gk0.cpu().numpy(), lam0[2:]).max() < ORACLE_TOL
+    assert _elem_rel(gp[0].cpu().numpy(), go).max() < ORACLE_TOL
