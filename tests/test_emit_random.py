@@ -20,15 +20,15 @@ from paper_2508_15967_amd import raygraph as rgb
 from tests.test_emit_host import _host_lib
 
 
-def _random_D(g, rng, n_terms):
-    x = [g.x(i) for i in range(3)]
-    k = [g.k(i) for i in range(3)]
+def _random_D(g, rng, n_terms, dim=3):
+    x = [g.x(i) for i in range(dim)]
+    k = [g.k(i) for i in range(dim)]
     om = g.omega
     s = g.param("s", 4)
     base = x + k
     sums = []
     for _ in range(4):
-        i, j = rng.choice(6, 2, replace=False)
+        i, j = rng.choice(2 * dim, 2, replace=False)
         c1, c2 = rng.choice([-2.0, -1.0, -0.5, 0.5, 1.0, 1.5, 2.0], 2)
         lin = c1 * base[i] + c2 * base[j]
         sums.append(lin)
@@ -36,13 +36,15 @@ def _random_D(g, rng, n_terms):
         sums.append(lin + float(rng.uniform(-1.0, 1.0)))
     gauss = []
     for _ in range(3):
-        i = int(rng.integers(0, 3))
+        i = int(rng.integers(0, dim))
         c, w = float(rng.uniform(-1.0, 1.0)), float(rng.uniform(1.0, 2.0))
         d = x[i] - c
         gauss.append((d * d * (-1.0 / (w * w))).exp())
     inv = [g.elem(s, j) for j in range(4)] + [om]
     pool = base + sums + gauss
-    D = k[0] * k[0] + k[1] * k[1] + k[2] * k[2] - om * om
+    D = -(om * om)
+    for ki in k:
+        D = D + ki * ki
     for _ in range(n_terms):
         nf = int(rng.integers(2, 4))
         fs = [pool[int(rng.integers(0, len(pool)))] for _ in range(nf)]
@@ -57,11 +59,13 @@ def _random_D(g, rng, n_terms):
     return D, x, k, om
 
 
-@pytest.mark.parametrize("seed,n_terms", [(0, 6), (1, 10), (2, 14), (3, 40), (4, 60), (5, 8), (6, 12), (7, 20)])
-def test_emitted_functions_match_graph(seed, n_terms):
+@pytest.mark.parametrize("seed,n_terms,dim", [(0, 6, 3), (1, 10, 3), (2, 14, 3), (3, 40, 3), (4, 60, 3),
+                                              (5, 8, 3), (6, 12, 3), (7, 20, 3), (8, 8, 2), (9, 50, 2)])
+def test_emitted_functions_match_graph(seed, n_terms, dim):
     rng = np.random.default_rng(seed)
-    g = rgb.Graph(3)
-    D, x, k, om = _random_D(g, rng, n_terms)
+    g = rgb.Graph(dim)
+    D, x, k, om = _random_D(g, rng, n_terms, dim)
+    ny = 2 * dim
     Dw = D.df(om)
     f_nodes = [-(D.df(ki)) / Dw for ki in k] + [D.df(xi) / Dw for xi in x]
     ys = x + k
@@ -77,31 +81,31 @@ def test_emitted_functions_match_graph(seed, n_terms):
     P_nodes = [[fi.df(g.elem(0, j)) for j in slots] for fi in f_nodes]
     params = [np.ascontiguousarray(rng.uniform(0.5, 1.5, 4))]
     n = 64
-    y = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (3, n)), rng.uniform(0.5, 1.5, (3, n))]))
+    y = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (dim, n)), rng.uniform(0.5, 1.5, (dim, n))]))
     omv = np.full(n, 1.5)
-    v = np.ascontiguousarray(rng.standard_normal((6, n)))
-    f_ref = np.zeros((6, n))
+    v = np.ascontiguousarray(rng.standard_normal((ny, n)))
+    f_ref = np.zeros((ny, n))
     D_ref = np.zeros(n)
-    jv_ref = np.zeros((6, n))
+    jv_ref = np.zeros((ny, n))
     gp_ref = np.zeros(len(slots))
     for r in range(n):
-        xv, kv = list(y[:3, r]), list(y[3:, r])
+        xv, kv = list(y[:dim, r]), list(y[dim:, r])
         ev = lambda nd: g.eval(nd, xv, kv, 1.5, params=params)
         D_ref[r] = ev(D)
         f_ref[:, r] = [ev(fi) for fi in f_nodes]
-        J = np.array([[ev(J_nodes[i][j]) for j in range(6)] for i in range(6)])
+        J = np.array([[ev(J_nodes[i][j]) for j in range(ny)] for i in range(ny)])
         jv_ref[:, r] = v[:, r] @ J
-        gp_ref += v[:, r] @ np.array([[ev(P_nodes[i][e]) for e in range(len(slots))] for i in range(6)])
+        gp_ref += v[:, r] @ np.array([[ev(P_nodes[i][e]) for e in range(len(slots))] for i in range(ny)])
     with tempfile.TemporaryDirectory() as tmp:
         lib = _host_lib(prog, True, tmp)
         pp = (C.c_void_p * 8)(params[0].ctypes.data, *([None] * 7))
-        f = np.zeros((6, n))
+        f = np.zeros((ny, n))
         Dv = np.zeros(n)
-        lib.host_eval(n, 6, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
+        lib.host_eval(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
                       C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
-        jv = np.zeros((6, n))
+        jv = np.zeros((ny, n))
         gp = np.zeros(64)
-        lib.host_vjp(n, 6, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
+        lib.host_vjp(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
                      C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
     assert np.abs(Dv - D_ref).max() <= 1e-13 * (1.0 + np.abs(D_ref).max())
     assert (np.abs(f - f_ref).max(axis=0) / np.abs(f_ref).max(axis=0)).max() < 1e-12

@@ -1,7 +1,7 @@
 """The GPU kernels on random dispersion relations (the generator of
 test_emit_random.py: shared sub-sums, scaled sums, Gaussians, omega and
-parameter elements; one relation small enough for the unrolled stages, one
-large enough for the rolled stages with the constant table).  The
+parameter elements; in 3-D and 2-D, relations small enough for the unrolled
+stages and large enough for the rolled stages with the constant table).  The
 reference is the same emitted functions built as host C++ (which
 test_emit_random.py checks against the graph's own derivatives), driven by
 a host RK4 loop and a host discrete RK4 adjoint written from the method's
@@ -28,7 +28,7 @@ def _host_rhs(lib, y, om, pp):
     n = y.shape[1]
     y = np.ascontiguousarray(y)
     f, D = np.zeros_like(y), np.zeros(n)
-    lib.host_eval(n, 6, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
+    lib.host_eval(n, y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
                   C.c_void_p(f.ctypes.data), C.c_void_p(D.ctypes.data))
     return f
 
@@ -36,27 +36,28 @@ def _host_rhs(lib, y, om, pp):
 def _host_vjp(lib, y, om, pp, v, gp):
     y, v = np.ascontiguousarray(y), np.ascontiguousarray(v)
     jv = np.zeros_like(y)
-    lib.host_vjp(y.shape[1], 6, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
+    lib.host_vjp(y.shape[1], y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
                  C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
     return jv
 
 
-@pytest.mark.parametrize("seed,n_terms", [(1, 10), (4, 60)])
-def test_random_relation_matches_host_build(seed, n_terms):
+@pytest.mark.parametrize("seed,n_terms,dim", [(1, 10, 3), (4, 60, 3), (8, 8, 2), (9, 50, 2)])
+def test_random_relation_matches_host_build(seed, n_terms, dim):
     torch = U.torch_mod()
     rng = np.random.default_rng(seed)
-    g = rgb.Graph(3)
-    D, _, _, _ = _random_D(g, rng, n_terms)
-    print(f"[case] random relation seed={seed} terms={n_terms}", flush=True)
+    g = rgb.Graph(dim)
+    D, _, _, _ = _random_D(g, rng, n_terms, dim)
+    ny = 2 * dim
+    print(f"[case] random relation seed={seed} terms={n_terms} dim={dim}", flush=True)
     prog = g.compile(D, want_adjoint=True)
     src = prog.source()
     ns = int(prog.info()["n_grad_slots"])
     elems = [int(t) for t in re.search(r"rg_grad_elem\[\d+\] = \{([^}]*)\}", src).group(1).split(",")][:ns]
     params = [np.ascontiguousarray(rng.uniform(0.5, 1.5, 4))]
     n, steps, dt = 512, 200, 1e-3
-    y0 = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (3, n)), rng.uniform(0.5, 1.5, (3, n))]))
+    y0 = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (dim, n)), rng.uniform(0.5, 1.5, (dim, n))]))
     om = np.full(n, 1.5)
-    target = rng.uniform(-1.0, 1.0, (3, n))
+    target = rng.uniform(-1.0, 1.0, (dim, n))
     with tempfile.TemporaryDirectory() as tmp:
         lib = _host_lib(prog, True, tmp)
         pp = (C.c_void_p * 8)(params[0].ctypes.data, *([None] * 7))
@@ -66,7 +67,7 @@ def test_random_relation_matches_host_build(seed, n_terms):
         scale = np.abs(fh).max(axis=0)
         assert (np.abs(fg.cpu().numpy() - fh).max(axis=0) / scale).max() < 1e-13
         # RK4 forward on the host, every stage state kept for the adjoint
-        Y = np.zeros((steps, 4, 6, n))
+        Y = np.zeros((steps, 4, ny, n))
         y = y0.copy()
         for s in range(steps):
             Y[s, 0] = y
@@ -79,7 +80,7 @@ def test_random_relation_matches_host_build(seed, n_terms):
             k4 = _host_rhs(lib, Y[s, 3], om, pp)
             y = y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
         # discrete adjoint of that map for L = sum |x_end - target|^2
-        lam = np.concatenate([2.0 * (y[:3] - target), np.zeros((3, n))])
+        lam = np.concatenate([2.0 * (y[:dim] - target), np.zeros((dim, n))])
         gp = np.zeros(64)
         for s in range(steps - 1, -1, -1):
             kb4 = dt / 6.0 * lam
@@ -91,20 +92,20 @@ def test_random_relation_matches_host_build(seed, n_terms):
             kb1 = dt / 6.0 * lam + 0.5 * dt * yb2
             yb1 = _host_vjp(lib, Y[s, 0], om, pp, kb1, gp)
             lam = lam + yb1 + yb2 + yb3 + yb4
-    x0, k0 = U.dev(y0[:3]), U.dev(y0[3:])
+    x0, k0 = U.dev(y0[:dim]), U.dev(y0[dim:])
     pt = [U.dev(params[0])]
     out = prog.trace(x0, k0, U.dev(om), pt, dt=dt, n_steps=steps, checkpoint_every=10)
     torch.cuda.synchronize()
     ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()},
-                          {"x": y[:3], "k": y[3:]}, om, 3)
+                          {"x": y[:dim], "k": y[dim:]}, om, dim)
     assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
     lx = (2.0 * (out["x"] - U.dev(target))).contiguous()
     gx0, gk0, gps = torch.empty_like(x0), torch.empty_like(k0), [torch.empty_like(pt[0])]
     prog.adjoint_desc(out["_desc"], lx, None, gx0, gk0, gps)
     torch.cuda.synchronize()
     rel = lambda a, b: np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
-    assert rel(gx0.cpu().numpy(), lam[:3]).max() < 1e-9
-    assert rel(gk0.cpu().numpy(), lam[3:]).max() < 1e-9
+    assert rel(gx0.cpu().numpy(), lam[:dim]).max() < 1e-9
+    assert rel(gk0.cpu().numpy(), lam[dim:]).max() < 1e-9
     if ns:
         ref = np.zeros(4)
         ref[elems] = gp[:ns]
