@@ -6,8 +6,8 @@ reference is the same emitted functions built as host C++ (which
 test_emit_random.py checks against the graph's own derivatives), driven by
 a host RK4 loop and a host discrete RK4 adjoint written from the method's
 definition: right-hand side and D at points to rounding, endpoints after
-200 steps to 1e-11 per ray, dL/dx0, dL/dk0 per ray and dL/dtheta to
-1e-9.  This covers the kernels' handling of programs other than the five
+200 steps and every 50th state to 1e-11 per ray, D along the rays,
+dL/dx0, dL/dk0 per ray and dL/dtheta to 1e-9.  This covers the kernels' handling of programs other than the five
 workload media."""
 import ctypes as C
 import re
@@ -24,13 +24,13 @@ from tests.test_emit_random import _random_D
 pytestmark = pytest.mark.gpu
 
 
-def _host_rhs(lib, y, om, pp):
+def _host_rhs(lib, y, om, pp, with_D=False):
     n = y.shape[1]
     y = np.ascontiguousarray(y)
     f, D = np.zeros_like(y), np.zeros(n)
     lib.host_eval(n, y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
                   C.c_void_p(f.ctypes.data), C.c_void_p(D.ctypes.data))
-    return f
+    return (f, D) if with_D else f
 
 
 def _host_vjp(lib, y, om, pp, v, gp):
@@ -66,10 +66,17 @@ def test_random_relation_matches_host_build(seed, n_terms, dim):
         fh = _host_rhs(lib, y0, om, pp)
         scale = np.abs(fh).max(axis=0)
         assert (np.abs(fg.cpu().numpy() - fh).max(axis=0) / scale).max() < 1e-13
-        # RK4 forward on the host, every stage state kept for the adjoint
+        # RK4 forward on the host, every stage state kept for the adjoint,
+        # every 50th state and D there kept as snapshots
         Y = np.zeros((steps, 4, ny, n))
+        snaps, snaps_D = [], []
         y = y0.copy()
-        for s in range(steps):
+        for s in range(steps + 1):
+            if s % 50 == 0:
+                snaps.append(y.copy())
+                snaps_D.append(_host_rhs(lib, y, om, pp, with_D=True)[1])
+            if s == steps:
+                break
             Y[s, 0] = y
             k1 = _host_rhs(lib, y, om, pp)
             Y[s, 1] = y + 0.5 * dt * k1
@@ -94,11 +101,16 @@ def test_random_relation_matches_host_build(seed, n_terms, dim):
             lam = lam + yb1 + yb2 + yb3 + yb4
     x0, k0 = U.dev(y0[:dim]), U.dev(y0[dim:])
     pt = [U.dev(params[0])]
-    out = prog.trace(x0, k0, U.dev(om), pt, dt=dt, n_steps=steps, checkpoint_every=10)
+    out = prog.trace(x0, k0, U.dev(om), pt, dt=dt, n_steps=steps, checkpoint_every=10, store=True,
+                     store_D=True, store_every=50)
     torch.cuda.synchronize()
     ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()},
                           {"x": y[:dim], "k": y[dim:]}, om, dim)
     assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
+    tx, tk = U.traj_errors(out["traj"].cpu().numpy(), np.stack(snaps), om, dim)
+    assert tx < U.TOL and tk < U.TOL, (tx, tk)
+    dref = np.stack(snaps_D)
+    assert np.abs(out["traj_D"].cpu().numpy() - dref).max() < 1e-12 * (1.0 + np.abs(dref).max())
     lx = (2.0 * (out["x"] - U.dev(target))).contiguous()
     gx0, gk0, gps = torch.empty_like(x0), torch.empty_like(k0), [torch.empty_like(pt[0])]
     prog.adjoint_desc(out["_desc"], lx, None, gx0, gk0, gps)
