@@ -392,3 +392,33 @@ def test_adjoint_of_rays_that_leave_the_box(oracle, mode):
     assert _ray_rel(gx0.cpu().numpy(), lam0[:2]).max() < ORACLE_TOL
     assert _ray_rel(gk0.cpu().numpy(), lam0[2:]).max() < ORACLE_TOL
     assert _elem_rel(gp[0].cpu().numpy(), go).max() < ORACLE_TOL
+
+
+@pytest.mark.parametrize("cfg,n,steps", [("2", 512, 500), ("1", 512, 500)])
+def test_adjoint_without_parameters_matches_oracle(oracle, cfg, n, steps):
+    """Media with no differentiable parameters, one of them (the
+    stratified medium) with wavevector components that stay fixed along a
+    ray (zero right-hand side, which the integrator and the emitter treat
+    as ray invariants): dL/dx0 and dL/dk0 per ray against the oracle's
+    adjoint, the fixed components' adjoints included."""
+    torch = U.torch_mod()
+    w = W.make(cfg, n)
+    w.n_steps = steps
+    w.targets = np.random.default_rng(7).uniform(-1.0, 1.0, w.x0.shape) + w.x0
+    print(f"[case] adjoint without parameters cfg={cfg} n={n} steps={steps}", flush=True)
+    _, _, prog, params = U.program(w, want_adjoint=True)
+    assert not params
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    out = prog.trace(x0, k0, om, [], dt=w.dt, n_steps=w.n_steps, checkpoint_every=100)
+    torch.cuda.synchronize()
+    o = oracle.trace(w)
+    ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()}, o, w.omega, w.dim)
+    assert ex.max() < U.TOL and ek.max() < U.TOL
+    lx = (2.0 * (out["x"] - U.dev(w.targets))).contiguous()
+    lk = (0.5 * out["k"]).contiguous()
+    gx0, gk0 = torch.empty_like(x0), torch.empty_like(k0)
+    prog.adjoint_desc(out["_desc"], lx, lk, gx0, gk0, [])
+    torch.cuda.synchronize()
+    lam0, _ = oracle.adjoint(w, np.concatenate([2 * (o["x"] - w.targets), 0.5 * o["k"]]))
+    assert _ray_rel(gx0.cpu().numpy(), lam0[:w.dim]).max() < ORACLE_TOL
+    assert _ray_rel(gk0.cpu().numpy(), lam0[w.dim:]).max() < ORACLE_TOL
