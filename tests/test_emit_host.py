@@ -60,6 +60,19 @@ extern "C" void host_eval_lit(int n, int ny, const double *y, const double *om, 
         D[r] = rg_D<true>(yy, om[r], 0.0, P);
     }
 }
+// with a time per point (time-dependent relations)
+extern "C" void host_eval_t(int n, int ny, const double *y, const double *om, const double *t,
+                            const double *const *pp, double *f, double *D) {
+    rg_P P; memset(&P, 0, sizeof P);
+    for (int i = 0; i < 8 && pp; i++) P.p[i] = pp[i];
+    for (int r = 0; r < n; r++) {
+        double yy[6], ff[6];
+        for (int c = 0; c < ny; c++) yy[c] = y[c * n + r];
+        rg_rhs(yy, om[r], t[r], P, ff);
+        for (int c = 0; c < ny; c++) f[c * n + r] = ff[c];
+        D[r] = rg_D(yy, om[r], t[r], P);
+    }
+}
 #ifdef HAS_F32
 extern "C" void host_eval32(int n, int ny, const float *y, const float *om, const double *const *pp,
                             float *f) {
@@ -83,6 +96,18 @@ extern "C" void host_vjp(int n, int ny, const double *y, const double *om, const
         double yy[6], vv[6], jj[6];
         for (int c = 0; c < ny; c++) { yy[c] = y[c * n + r]; vv[c] = v[c * n + r]; }
         rg_vjp(yy, om[r], 0.0, P, vv, jj, gp, G);
+        for (int c = 0; c < ny; c++) jv[c * n + r] = jj[c];
+    }
+}
+extern "C" void host_vjp_t(int n, int ny, const double *y, const double *om, const double *t,
+                           const double *const *pp, const double *v, double *jv, double *gp) {
+    rg_P P; memset(&P, 0, sizeof P);
+    for (int i = 0; i < 8 && pp; i++) P.p[i] = pp[i];
+    rg_GA G;
+    for (int r = 0; r < n; r++) {
+        double yy[6], vv[6], jj[6];
+        for (int c = 0; c < ny; c++) { yy[c] = y[c * n + r]; vv[c] = v[c * n + r]; }
+        rg_vjp(yy, om[r], t[r], P, vv, jj, gp, G);
         for (int c = 0; c < ny; c++) jv[c * n + r] = jj[c];
     }
 }

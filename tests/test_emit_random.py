@@ -4,7 +4,8 @@ vector-Jacobian product v^T df/dy of the emitted device functions, compiled
 as host C++, against the graph front end's own evaluation of the same
 symbolic derivatives taken on the unfactored graph.  The random relations
 are sums of products over a pool that shares sub-sums, scaled copies of
-sums, Gaussians and ray invariants (omega, parameter elements), so that the
+sums, Gaussians, ray invariants (omega, parameter elements) and, in some,
+the time t, so that the
 common-factor, scaled-sum, product and division passes all rewrite them;
 a pass that drops a term, flips a sign or mixes up an operand changes the
 values far beyond rounding.  The larger relations carry enough constants
@@ -20,7 +21,7 @@ from paper_2508_15967_amd import raygraph as rgb
 from tests.test_emit_host import _host_lib
 
 
-def _random_D(g, rng, n_terms, dim=3):
+def _random_D(g, rng, n_terms, dim=3, with_t=False):
     x = [g.x(i) for i in range(dim)]
     k = [g.k(i) for i in range(dim)]
     om = g.omega
@@ -42,6 +43,8 @@ def _random_D(g, rng, n_terms, dim=3):
         gauss.append((d * d * (-1.0 / (w * w))).exp())
     inv = [g.elem(s, j) for j in range(4)] + [om]
     pool = base + sums + gauss
+    if with_t:  # time-dependent factors
+        pool += [(0.7 * g.t + 0.2).sin(), 0.5 * g.t + 1.0, (x[0] - 0.3 * g.t).cos()]
     D = -(om * om)
     for ki in k:
         D = D + ki * ki
@@ -59,12 +62,14 @@ def _random_D(g, rng, n_terms, dim=3):
     return D, x, k, om
 
 
-@pytest.mark.parametrize("seed,n_terms,dim", [(0, 6, 3), (1, 10, 3), (2, 14, 3), (3, 40, 3), (4, 60, 3),
-                                              (5, 8, 3), (6, 12, 3), (7, 20, 3), (8, 8, 2), (9, 50, 2)])
-def test_emitted_functions_match_graph(seed, n_terms, dim):
+@pytest.mark.parametrize("seed,n_terms,dim,with_t", [
+    (0, 6, 3, False), (1, 10, 3, False), (2, 14, 3, False), (3, 40, 3, False), (4, 60, 3, False),
+    (5, 8, 3, False), (6, 12, 3, False), (7, 20, 3, False), (8, 8, 2, False), (9, 50, 2, False),
+    (10, 12, 3, True), (11, 40, 2, True)])
+def test_emitted_functions_match_graph(seed, n_terms, dim, with_t):
     rng = np.random.default_rng(seed)
     g = rgb.Graph(dim)
-    D, x, k, om = _random_D(g, rng, n_terms, dim)
+    D, x, k, om = _random_D(g, rng, n_terms, dim, with_t)
     ny = 2 * dim
     Dw = D.df(om)
     f_nodes = [-(D.df(ki)) / Dw for ki in k] + [D.df(xi) / Dw for xi in x]
@@ -83,6 +88,7 @@ def test_emitted_functions_match_graph(seed, n_terms, dim):
     n = 64
     y = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (dim, n)), rng.uniform(0.5, 1.5, (dim, n))]))
     omv = np.full(n, 1.5)
+    tv = np.ascontiguousarray(rng.uniform(0.0, 3.0, n) if with_t else np.zeros(n))
     v = np.ascontiguousarray(rng.standard_normal((ny, n)))
     f_ref = np.zeros((ny, n))
     D_ref = np.zeros(n)
@@ -90,7 +96,7 @@ def test_emitted_functions_match_graph(seed, n_terms, dim):
     gp_ref = np.zeros(len(slots))
     for r in range(n):
         xv, kv = list(y[:dim, r]), list(y[dim:, r])
-        ev = lambda nd: g.eval(nd, xv, kv, 1.5, params=params)
+        ev = lambda nd: g.eval(nd, xv, kv, 1.5, t=float(tv[r]), params=params)
         D_ref[r] = ev(D)
         f_ref[:, r] = [ev(fi) for fi in f_nodes]
         J = np.array([[ev(J_nodes[i][j]) for j in range(ny)] for i in range(ny)])
@@ -101,12 +107,13 @@ def test_emitted_functions_match_graph(seed, n_terms, dim):
         pp = (C.c_void_p * 8)(params[0].ctypes.data, *([None] * 7))
         f = np.zeros((ny, n))
         Dv = np.zeros(n)
-        lib.host_eval(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
-                      C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
+        lib.host_eval_t(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data),
+                        C.c_void_p(tv.ctypes.data), pp, C.c_void_p(f.ctypes.data), C.c_void_p(Dv.ctypes.data))
         jv = np.zeros((ny, n))
         gp = np.zeros(64)
-        lib.host_vjp(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data), pp,
-                     C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
+        lib.host_vjp_t(n, ny, C.c_void_p(y.ctypes.data), C.c_void_p(omv.ctypes.data),
+                       C.c_void_p(tv.ctypes.data), pp, C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data),
+                       C.c_void_p(gp.ctypes.data))
     assert np.abs(Dv - D_ref).max() <= 1e-13 * (1.0 + np.abs(D_ref).max())
     assert (np.abs(f - f_ref).max(axis=0) / np.abs(f_ref).max(axis=0)).max() < 1e-12
     assert (np.abs(jv - jv_ref).max(axis=0) / np.abs(jv_ref).max(axis=0)).max() < 1e-11

@@ -1,7 +1,8 @@
 """The GPU kernels on random dispersion relations (the generator of
 test_emit_random.py: shared sub-sums, scaled sums, Gaussians, omega and
-parameter elements; in 3-D and 2-D, relations small enough for the unrolled
-stages and large enough for the rolled stages with the constant table).  The
+parameter elements, in two of them the time t with launch times t0 != 0;
+in 3-D and 2-D, relations small enough for the unrolled stages and large
+enough for the rolled stages with the constant table).  The
 reference is the same emitted functions built as host C++ (which
 test_emit_random.py checks against the graph's own derivatives), driven by
 a host RK4 loop and a host discrete RK4 adjoint written from the method's
@@ -24,31 +25,33 @@ from tests.test_emit_random import _random_D
 pytestmark = pytest.mark.gpu
 
 
-def _host_rhs(lib, y, om, pp, with_D=False):
+def _host_rhs(lib, y, om, t, pp, with_D=False):
     n = y.shape[1]
-    y = np.ascontiguousarray(y)
+    y, t = np.ascontiguousarray(y), np.ascontiguousarray(t)
     f, D = np.zeros_like(y), np.zeros(n)
-    lib.host_eval(n, y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
-                  C.c_void_p(f.ctypes.data), C.c_void_p(D.ctypes.data))
+    lib.host_eval_t(n, y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data),
+                    C.c_void_p(t.ctypes.data), pp, C.c_void_p(f.ctypes.data), C.c_void_p(D.ctypes.data))
     return (f, D) if with_D else f
 
 
-def _host_vjp(lib, y, om, pp, v, gp):
-    y, v = np.ascontiguousarray(y), np.ascontiguousarray(v)
+def _host_vjp(lib, y, om, t, pp, v, gp):
+    y, v, t = np.ascontiguousarray(y), np.ascontiguousarray(v), np.ascontiguousarray(t)
     jv = np.zeros_like(y)
-    lib.host_vjp(y.shape[1], y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), pp,
-                 C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
+    lib.host_vjp_t(y.shape[1], y.shape[0], C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data),
+                   C.c_void_p(t.ctypes.data), pp, C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data),
+                   C.c_void_p(gp.ctypes.data))
     return jv
 
 
-@pytest.mark.parametrize("seed,n_terms,dim", [(1, 10, 3), (4, 60, 3), (8, 8, 2), (9, 50, 2)])
-def test_random_relation_matches_host_build(seed, n_terms, dim):
+@pytest.mark.parametrize("seed,n_terms,dim,with_t", [(1, 10, 3, False), (4, 60, 3, False), (8, 8, 2, False),
+                                                     (9, 50, 2, False), (10, 12, 3, True), (11, 40, 2, True)])
+def test_random_relation_matches_host_build(seed, n_terms, dim, with_t):
     torch = U.torch_mod()
     rng = np.random.default_rng(seed)
     g = rgb.Graph(dim)
-    D, _, _, _ = _random_D(g, rng, n_terms, dim)
+    D, _, _, _ = _random_D(g, rng, n_terms, dim, with_t)
     ny = 2 * dim
-    print(f"[case] random relation seed={seed} terms={n_terms} dim={dim}", flush=True)
+    print(f"[case] random relation seed={seed} terms={n_terms} dim={dim} t={with_t}", flush=True)
     prog = g.compile(D, want_adjoint=True)
     src = prog.source()
     ns = int(prog.info()["n_grad_slots"])
@@ -57,13 +60,14 @@ def test_random_relation_matches_host_build(seed, n_terms, dim):
     n, steps, dt = 512, 200, 1e-3
     y0 = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (dim, n)), rng.uniform(0.5, 1.5, (dim, n))]))
     om = np.full(n, 1.5)
+    t0 = rng.uniform(0.0, 3.0, n) if with_t else np.zeros(n)
     target = rng.uniform(-1.0, 1.0, (dim, n))
     with tempfile.TemporaryDirectory() as tmp:
         lib = _host_lib(prog, True, tmp)
         pp = (C.c_void_p * 8)(params[0].ctypes.data, *([None] * 7))
         # right-hand side and D at points
-        fg, Dg = prog.eval(U.dev(y0), U.dev(om), [U.dev(params[0])])
-        fh = _host_rhs(lib, y0, om, pp)
+        fg, Dg = prog.eval(U.dev(y0), U.dev(om), [U.dev(params[0])], t=U.dev(t0))
+        fh = _host_rhs(lib, y0, om, t0, pp)
         scale = np.abs(fh).max(axis=0)
         assert (np.abs(fg.cpu().numpy() - fh).max(axis=0) / scale).max() < 1e-13
         # RK4 forward on the host, every stage state kept for the adjoint,
@@ -71,39 +75,45 @@ def test_random_relation_matches_host_build(seed, n_terms, dim):
         Y = np.zeros((steps, 4, ny, n))
         snaps, snaps_D = [], []
         y = y0.copy()
+        T = np.zeros((steps + 1, n))  # time of each step's start, as the integrator accumulates it
+        T[0] = t0
         for s in range(steps + 1):
             if s % 50 == 0:
                 snaps.append(y.copy())
-                snaps_D.append(_host_rhs(lib, y, om, pp, with_D=True)[1])
+                snaps_D.append(_host_rhs(lib, y, om, T[s], pp, with_D=True)[1])
             if s == steps:
                 break
+            t, th = T[s], T[s] + 0.5 * dt
             Y[s, 0] = y
-            k1 = _host_rhs(lib, y, om, pp)
+            k1 = _host_rhs(lib, y, om, t, pp)
             Y[s, 1] = y + 0.5 * dt * k1
-            k2 = _host_rhs(lib, Y[s, 1], om, pp)
+            k2 = _host_rhs(lib, Y[s, 1], om, th, pp)
             Y[s, 2] = y + 0.5 * dt * k2
-            k3 = _host_rhs(lib, Y[s, 2], om, pp)
+            k3 = _host_rhs(lib, Y[s, 2], om, th, pp)
             Y[s, 3] = y + dt * k3
-            k4 = _host_rhs(lib, Y[s, 3], om, pp)
+            k4 = _host_rhs(lib, Y[s, 3], om, t + dt, pp)
             y = y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            T[s + 1] = T[s] + dt
         # discrete adjoint of that map for L = sum |x_end - target|^2
         lam = np.concatenate([2.0 * (y[:dim] - target), np.zeros((dim, n))])
         gp = np.zeros(64)
         for s in range(steps - 1, -1, -1):
+            t, th = T[s], T[s] + 0.5 * dt
             kb4 = dt / 6.0 * lam
-            yb4 = _host_vjp(lib, Y[s, 3], om, pp, kb4, gp)
+            yb4 = _host_vjp(lib, Y[s, 3], om, t + dt, pp, kb4, gp)
             kb3 = dt / 3.0 * lam + dt * yb4
-            yb3 = _host_vjp(lib, Y[s, 2], om, pp, kb3, gp)
+            yb3 = _host_vjp(lib, Y[s, 2], om, th, pp, kb3, gp)
             kb2 = dt / 3.0 * lam + 0.5 * dt * yb3
-            yb2 = _host_vjp(lib, Y[s, 1], om, pp, kb2, gp)
+            yb2 = _host_vjp(lib, Y[s, 1], om, th, pp, kb2, gp)
             kb1 = dt / 6.0 * lam + 0.5 * dt * yb2
-            yb1 = _host_vjp(lib, Y[s, 0], om, pp, kb1, gp)
+            yb1 = _host_vjp(lib, Y[s, 0], om, t, pp, kb1, gp)
             lam = lam + yb1 + yb2 + yb3 + yb4
     x0, k0 = U.dev(y0[:dim]), U.dev(y0[dim:])
     pt = [U.dev(params[0])]
     out = prog.trace(x0, k0, U.dev(om), pt, dt=dt, n_steps=steps, checkpoint_every=10, store=True,
-                     store_D=True, store_every=50)
+                     store_D=True, store_every=50, t0=U.dev(t0))
     torch.cuda.synchronize()
+    assert np.abs(out["t"].cpu().numpy() - T[steps]).max() <= 1e-13 * (1.0 + T[steps].max())
     ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()},
                           {"x": y[:dim], "k": y[dim:]}, om, dim)
     assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
