@@ -133,3 +133,77 @@ def test_random_relation_matches_host_build(seed, n_terms, dim, with_t):
         ref[elems] = gp[:ns]
         got = gps[0].cpu().numpy()
         assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max(), (got, ref)
+
+
+def _dp_factor(err, facmax):
+    """The step factor of the Dormand-Prince controller: k/32 for the
+    largest integer k in [0, 161] with err (5k)^5 <= 144^5 (0.9 err^(-1/5)
+    rounded down to a multiple of 1/32), clipped to [0.2, facmax]."""
+    ks = np.arange(162, dtype=np.float64)
+    with np.errstate(invalid="ignore"):  # inf * 0 for k = 0: not within
+        ok = err[:, None] * (5.0 * ks[None, :]) ** 5 <= 144.0 ** 5
+    k = np.where(ok.any(axis=1), 161 - np.argmax(ok[:, ::-1], axis=1), 0)
+    return np.minimum(np.maximum(k / 32.0, 0.2), facmax)
+
+
+@pytest.mark.parametrize("seed,n_terms,dim,with_t", [(4, 60, 3, False), (11, 40, 2, True)])
+def test_random_relation_dopri_matches_host_build(oracle, seed, n_terms, dim, with_t):
+    """Dormand-Prince 5(4) on random relations (its stages take the
+    constants as literals; the rolled RK4 stages read them from the table):
+    every ray's accepted steps, attempts and status equal to a host
+    Dormand-Prince with the same controller over the same emitted
+    functions built for the host, and endpoints and end times to 1e-11."""
+    torch = U.torch_mod()
+    rng = np.random.default_rng(seed)
+    g = rgb.Graph(dim)
+    D, _, _, _ = _random_D(g, rng, n_terms, dim, with_t)
+    ny = 2 * dim
+    print(f"[case] random relation Dormand-Prince seed={seed} dim={dim} t={with_t}", flush=True)
+    prog = g.compile(D)
+    params = [np.ascontiguousarray(rng.uniform(0.5, 1.5, 4))]
+    n, budget, h0, tol, hmin = 256, 60, 1e-2, 1e-9, 1e-12
+    y0 = np.ascontiguousarray(np.concatenate([rng.uniform(-1.0, 1.0, (dim, n)), rng.uniform(0.5, 1.5, (dim, n))]))
+    om = np.full(n, 1.5)
+    t0 = rng.uniform(0.0, 3.0, n) if with_t else np.zeros(n)
+    c, a, b5, b4 = oracle.dopri_tableau()
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, False, tmp)
+        pp = (C.c_void_p * 8)(params[0].ctypes.data, *([None] * 7))
+        y, t = y0.copy(), t0.copy()
+        h, fm = np.full(n, h0), np.full(n, 5.0)
+        acc, att, st = np.zeros(n, np.int64), np.zeros(n, np.int64), np.full(n, -1)
+        k1 = _host_rhs(lib, y, om, t, pp)
+        while (st < 0).any():
+            st[(st < 0) & ((acc >= budget) | (att >= 4 * budget))] = rgb.RAY_BUDGET
+            r = np.nonzero(st < 0)[0]
+            if r.size == 0:
+                break
+            hs, yr, tr, omr = h[r], y[:, r], t[r], om[r]
+            K = [k1[:, r]]
+            for i in range(1, 7):
+                Yi = yr + hs * sum(a[i, j] * K[j] for j in range(i))
+                K.append(_host_rhs(lib, Yi, omr, tr + c[i] * hs, pp))
+            y5 = yr + hs * sum(b5[j] * K[j] for j in range(7))
+            e = hs * sum((b5[j] - b4[j]) * K[j] for j in range(7))
+            sc = tol + tol * np.maximum(np.abs(yr), np.abs(y5))
+            err = np.sqrt(((e / sc) ** 2).sum(axis=0) / ny)
+            att[r] += 1
+            ok = (err <= 1.0) & np.isfinite(y5).all(axis=0) & np.isfinite(K[6]).all(axis=0)
+            fac = _dp_factor(np.where(ok, err, np.where(err > 1.0, err, np.inf)), np.where(ok, fm[r], 1.0))
+            h[r] = hs * fac
+            ra = r[ok]
+            y[:, ra], k1[:, ra] = y5[:, ok], K[6][:, ok]
+            t[ra] = t[ra] + hs[ok]
+            acc[ra] += 1
+            fm[r] = np.where(ok, 5.0, 1.0)
+            st[r[h[r] < hmin]] = rgb.RAY_STEP_UNDERFLOW
+    out = prog.trace(U.dev(y0[:dim]), U.dev(y0[dim:]), U.dev(om), [U.dev(params[0])], integrator=rgb.DOPRI54,
+                     h0=h0, rtol=tol, atol=tol, hmin=hmin, max_steps=budget, t0=U.dev(t0))
+    torch.cuda.synchronize()
+    assert np.array_equal(out["status"].cpu().numpy(), st)
+    assert np.array_equal(out["steps"].cpu().numpy(), acc) and np.array_equal(out["attempts"].cpu().numpy(), att)
+    assert (att > acc).any()  # some attempts were rejected
+    ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()},
+                          {"x": y[:dim], "k": y[dim:]}, om, dim)
+    assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
+    assert np.abs(out["t"].cpu().numpy() - t).max() <= 1e-11 * (1.0 + np.abs(t).max())
