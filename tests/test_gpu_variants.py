@@ -290,3 +290,49 @@ def test_trace_stats_and_kernel_time():
     st2 = prog2.trace_stats(g2["_t"]["_desc"])
     assert st2["by_status"][0] == 3000 and st2["steps"] == 3000 * 200 and st2["attempts"] == 0
     assert st2["max_steps"] == 200
+
+
+@pytest.mark.parametrize("cfg", ["2", "3"])
+def test_hipgraph_replays_match_eager(cfg):
+    """One descriptor traced again and again with use_hipgraph: the first
+    call captures the launch sequence (for Dormand-Prince the fill kernel
+    that resets the refill queue, then the persistent kernel), the later
+    calls replay the cached graph.  Between the replays the program runs
+    eager work (a direct trace and a point evaluation) and the host
+    synchronises; the outputs are overwritten with NaN before each replay,
+    and every replay equals the eager trace bitwise."""
+    torch = U.torch_mod()
+    w = W.make(cfg, 3000)
+    if cfg == "2":
+        w.n_steps = 300
+    print(f"[case] hipgraph replays cfg={cfg}", flush=True)
+    launch = dict(block=256, rays_per_lane=1) if cfg == "2" else dict(block=128, compact_interval=32)
+    eager = U.gpu_trace(w, **launch)
+    _, _, prog, params = U.program(w)
+    x0, k0, om = U.dev(w.x0), U.dev(w.k0), U.dev(w.omega)
+    args = dict(integrator=w.integrator, dt=w.dt, n_steps=w.n_steps, h0=w.h0, rtol=w.rtol, atol=w.atol,
+                hmin=w.hmin, use_hipgraph=True, **launch)
+    if w.budget is not None:
+        args["budget"] = U.dev(w.budget.astype(np.int32))
+    if w.box_lo is not None:
+        args["box"] = (list(w.box_lo), list(w.box_hi))
+    out = {"x": torch.empty((3, w.n), dtype=torch.float64, device="cuda"),
+           "k": torch.empty((3, w.n), dtype=torch.float64, device="cuda"),
+           "t": torch.empty(w.n, dtype=torch.float64, device="cuda"),
+           "status": torch.empty(w.n, dtype=torch.int32, device="cuda"),
+           "steps": torch.empty(w.n, dtype=torch.int32, device="cuda")}
+    d = prog.make_desc(x0, k0, om, [], x_out=out["x"], k_out=out["k"], t_out=out["t"],
+                       status_out=out["status"], steps_out=out["steps"], **args)
+    y = U.dev(np.concatenate([w.x0[:, :64], w.k0[:, :64]]))
+    for rep in range(4):
+        for v in out.values():
+            v.fill_(-1 if v.dtype == torch.int32 else float("nan"))
+        torch.cuda.synchronize()
+        prog.trace_desc(d)
+        torch.cuda.synchronize()
+        for key in ("x", "k", "t", "status", "steps"):
+            assert np.array_equal(out[key].cpu().numpy(), eager[key]), (rep, key)
+        # eager work of the same program between the replays
+        U.gpu_trace(w, **launch)
+        prog.eval(y, U.dev(w.omega[:64]))
+        torch.cuda.synchronize()
