@@ -2,6 +2,7 @@
 include/raygraph.h declares; host-only error paths return the documented
 status codes; hipRTC compiles generated programs for gfx950."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -97,3 +98,61 @@ def test_trace_workspace_sizes_on_the_host():
     small = rgb.TraceDesc()
     small.struct_size = 4
     assert rgb._lib.rg_workspace_size(prog.h, C.byref(small), C.byref(C.c_size_t())) == rgb.RG_EINVAL
+
+
+def test_graph_api_random_calls():
+    """Random sequences of node-builder, df, eval, rendering and compile
+    calls, valid and invalid (unknown kinds and operations, node ids out of
+    range, parameters of length 0, non-finite constants): every call
+    returns a status, the library never crashes, and whatever builds a
+    relation in omega compiles (the emitter on arbitrary graphs)."""
+    import random
+    lib = rgb._lib
+    rng = random.Random(0)
+    vals = [0.0, -0.0, 1.0, -1.0, 2.0, 0.5, 1e300, -1e300, 1e-310, math.inf, -math.inf, math.nan, 3.7]
+    out = C.c_uint32()
+    compiled = 0
+    for it in range(80):
+        g = rgb.Graph(rng.choice([2, 3]))
+        nodes = []
+
+        def pick():
+            return rng.choice(nodes) if nodes and rng.random() < 0.9 else rng.randint(0, 10 ** 6)
+        for i in range(rng.randint(1, 60)):
+            r = rng.random()
+            if r < 0.2:
+                st = lib.rg_node_var(g.h, rng.randint(-1, 4), C.c_uint32(rng.randint(0, 3)), C.byref(out))
+            elif r < 0.35:
+                st = lib.rg_node_const(g.h, C.c_double(rng.choice(vals)), C.byref(out))
+            elif r < 0.55:
+                st = lib.rg_node_unary(g.h, rng.randint(-1, 6), C.c_uint32(pick()), C.byref(out))
+            elif r < 0.8:
+                st = lib.rg_node_binary(g.h, rng.randint(-1, 4), C.c_uint32(pick()), C.c_uint32(pick()),
+                                        C.byref(out))
+            elif r < 0.88:
+                st = lib.rg_node_powi(g.h, C.c_uint32(pick()), C.c_int32(rng.randint(-4, 6)), C.byref(out))
+            elif r < 0.95 and nodes:
+                st = lib.rg_df(g.h, C.c_uint32(rng.choice(nodes)), C.c_uint32(rng.choice(nodes)), C.byref(out))
+            else:
+                pidx = C.c_uint32()
+                st = lib.rg_node_param(g.h, b"p%d" % i, C.c_uint32(rng.randint(0, 5)), C.byref(pidx))
+                if st == rgb.RG_OK:
+                    st = lib.rg_node_elem(g.h, pidx, C.c_uint32(rng.randint(0, 6)), C.byref(out))
+            assert st in (rgb.RG_OK, rgb.RG_EINVAL), st
+            if st == rgb.RG_OK:
+                nodes.append(out.value)
+        for n in nodes[-3:]:
+            x = (C.c_double * 3)(*[rng.uniform(-2, 2) for _ in range(3)])
+            k = (C.c_double * 3)(*[rng.uniform(-2, 2) for _ in range(3)])
+            res = C.c_double()
+            lib.rg_eval(g.h, C.c_uint32(n), x, k, C.c_double(1.3), C.c_double(0.2), None, C.byref(res))
+            buf, need = C.create_string_buffer(64), C.c_size_t()
+            assert lib.rg_node_to_string(g.h, C.c_uint32(n), buf, C.c_size_t(64), C.byref(need)) == rgb.RG_OK
+        if nodes and rng.random() < 0.3:
+            try:
+                p = g.compile(rgb.Node(g, rng.choice(nodes)), want_adjoint=rng.random() < 0.5, compile_only=True)
+                assert p.info()["source_hash"] != 0
+                compiled += 1
+            except rgb.RayGraphError as e:
+                assert e.status in (rgb.RG_EINVAL, rgb.RG_EUNSUPPORTED), e
+    assert compiled > 0
