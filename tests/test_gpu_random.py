@@ -2,14 +2,15 @@
 test_emit_random.py: shared sub-sums, scaled sums, Gaussians, omega and
 parameter elements, in two of them the time t with launch times t0 != 0;
 in 3-D and 2-D, relations small enough for the unrolled stages and large
-enough for the rolled stages with the constant table).  The
-reference is the same emitted functions built as host C++ (which
-test_emit_random.py checks against the graph's own derivatives), driven by
-a host RK4 loop and a host discrete RK4 adjoint written from the method's
-definition: right-hand side and D at points to rounding, endpoints after
-200 steps and every 50th state to 1e-11 per ray, D along the rays,
-dL/dx0, dL/dk0 per ray and dL/dtheta to 1e-9.  This covers the kernels' handling of programs other than the five
-workload media."""
+enough for the rolled stages with the constant table).  The reference is
+the same emitted functions built as host C++ (which test_emit_random.py
+checks against the graph's own derivatives), driven by a host RK4 loop, a
+host discrete RK4 adjoint and a host Dormand-Prince controller written
+from the method's definition: right-hand side and D at points to
+rounding, endpoints after 200 steps and every 50th state to 1e-11 per ray,
+D along the rays, dL/dx0, dL/dk0 per ray and dL/dtheta to 1e-9, and the
+Dormand-Prince step counts, attempts and statuses exactly.  This covers
+the kernels' handling of programs other than the five workload media."""
 import ctypes as C
 import re
 import tempfile
