@@ -8,8 +8,9 @@ checks against the graph's own derivatives), driven by a host RK4 loop, a
 host discrete RK4 adjoint and a host Dormand-Prince controller written
 from the method's definition: right-hand side and D at points to
 rounding, endpoints after 200 steps and every 50th state to 1e-11 per ray,
-D along the rays, dL/dx0, dL/dk0 per ray and dL/dtheta to 1e-9, and the
-Dormand-Prince step counts, attempts and statuses exactly.  This covers
+D along the rays, dL/dx0, dL/dk0 per ray and dL/dtheta to 1e-9, the
+Dormand-Prince step counts, attempts and statuses exactly, and the Newton
+launch conditions against a host Newton over the graph's own derivative.  This covers
 the kernels' handling of programs other than the five workload media."""
 import ctypes as C
 import re
@@ -208,3 +209,48 @@ def test_random_relation_dopri_matches_host_build(oracle, seed, n_terms, dim, wi
                           {"x": y[:dim], "k": y[dim:]}, om, dim)
     assert ex.max() < U.TOL and ek.max() < U.TOL, (ex.max(), ek.max())
     assert np.abs(out["t"].cpu().numpy() - t).max() <= 1e-11 * (1.0 + np.abs(t).max())
+
+
+@pytest.mark.parametrize("seed,n_terms,dim", [(1, 10, 3), (8, 8, 2), (4, 60, 3)])
+def test_random_relation_newton_matches_host(seed, n_terms, dim):
+    """Launch conditions on random relations: the GPU Newton solve for k_x
+    (rg_solve_k, emitted D and dD/dk) against a host Newton iteration over
+    the graph's own D and dD/dk_x, from the same initial guesses: the rays
+    the host solves to |D| <= 1e-13 the GPU solves too, to the same root
+    (1e-12 relative), with |D| <= 1e-13 reported and the maximum over the
+    rays reduced on the GPU.  (Rays the host needs more than 20 iterations
+    for sit near a double root, where rounding can move the iterates
+    apart; they are left out.)"""
+    torch = U.torch_mod()
+    rng = np.random.default_rng(seed)
+    g = rgb.Graph(dim)
+    D, x, k, om = _random_D(g, rng, n_terms, dim)
+    dD = D.df(k[0])
+    print(f"[case] random relation Newton seed={seed} dim={dim}", flush=True)
+    prog = g.compile(D)
+    params = [np.ascontiguousarray(rng.uniform(0.5, 1.5, 4))]
+    n, tol = 256, 1e-13
+    X = rng.uniform(-1.0, 1.0, (dim, n))
+    K = np.concatenate([np.ones((1, n)), rng.uniform(0.1, 0.4, (dim - 1, n))])
+    root, solved = K[0].copy(), np.zeros(n, bool)
+    for r in range(n):
+        kv, xv = list(K[:, r]), list(X[:, r])
+        for it in range(51):
+            Dv = g.eval(D, xv, kv, 1.5, params=params)
+            if abs(Dv) <= tol:
+                solved[r] = it <= 20  # well-conditioned: quadratic convergence reached the root
+                break
+            if it == 50:
+                break
+            kv[0] -= Dv / g.eval(dD, xv, kv, 1.5, params=params)
+        root[r] = kv[0]
+    assert solved.mean() > 0.8
+    kd = U.dev(K)
+    it, Dg, mx = prog.solve_k(U.dev(X), kd, U.dev(np.full(n, 1.5)), [U.dev(params[0])], component=0, tol=tol)
+    torch.cuda.synchronize()
+    it, Dg, kg = it.cpu().numpy(), Dg.cpu().numpy(), kd.cpu().numpy()
+    assert (it[solved] >= 0).all() and (np.abs(Dg[solved]) <= tol).all()
+    assert np.abs(kg[0, solved] - root[solved]).max() < 1e-12 * np.abs(root[solved]).max()
+    assert np.array_equal(kg[1:], K[1:])  # the other components untouched
+    fin = np.isfinite(Dg)
+    assert float(mx.cpu()[0]) == (np.abs(Dg).max() if fin.all() else np.inf)
