@@ -5,7 +5,8 @@ as host C++, against the graph front end's own evaluation of the same
 symbolic derivatives taken on the unfactored graph.  The random relations
 are sums of products over a pool that shares sub-sums, scaled copies of
 sums, Gaussians, ray invariants (omega, parameter elements) and, in some,
-the time t, so that the
+the time t or square roots, logarithms, integer powers, sines and
+quotients of positive expressions, so that the
 common-factor, scaled-sum, product and division passes all rewrite them;
 a pass that drops a term, flips a sign or mixes up an operand changes the
 values far beyond rounding.  The larger relations carry enough constants
@@ -21,7 +22,7 @@ from paper_2508_15967_amd import raygraph as rgb
 from tests.test_emit_host import _host_lib
 
 
-def _random_D(g, rng, n_terms, dim=3, with_t=False):
+def _random_D(g, rng, n_terms, dim=3, with_t=False, rich=False):
     x = [g.x(i) for i in range(dim)]
     k = [g.k(i) for i in range(dim)]
     om = g.omega
@@ -45,6 +46,12 @@ def _random_D(g, rng, n_terms, dim=3, with_t=False):
     pool = base + sums + gauss
     if with_t:  # time-dependent factors
         pool += [(0.7 * g.t + 0.2).sin(), 0.5 * g.t + 1.0, (x[0] - 0.3 * g.t).cos()]
+    if rich:  # square roots, logarithms, integer powers and quotients of positive expressions
+        pos = [xi * xi + 1.5 for xi in x] + [(k[0] - 0.2 * x[-1]) ** 2 + 0.5]
+        for _ in range(4):
+            p1, p2 = pos[int(rng.integers(0, len(pos)))], pos[int(rng.integers(0, len(pos)))]
+            pool += [p1.sqrt(), p1.log(), p1 ** int(rng.choice([-2, -1, 2, 3])), base[int(rng.integers(0, 2 * dim))] / p2,
+                     (base[int(rng.integers(0, 2 * dim))] * 0.7).sin()]
     D = -(om * om)
     for ki in k:
         D = D + ki * ki
@@ -62,14 +69,15 @@ def _random_D(g, rng, n_terms, dim=3, with_t=False):
     return D, x, k, om
 
 
-@pytest.mark.parametrize("seed,n_terms,dim,with_t", [
-    (0, 6, 3, False), (1, 10, 3, False), (2, 14, 3, False), (3, 40, 3, False), (4, 60, 3, False),
-    (5, 8, 3, False), (6, 12, 3, False), (7, 20, 3, False), (8, 8, 2, False), (9, 50, 2, False),
-    (10, 12, 3, True), (11, 40, 2, True)])
-def test_emitted_functions_match_graph(seed, n_terms, dim, with_t):
+@pytest.mark.parametrize("seed,n_terms,dim,extra", [
+    (0, 6, 3, ""), (1, 10, 3, ""), (2, 14, 3, ""), (3, 40, 3, ""), (4, 60, 3, ""),
+    (5, 8, 3, ""), (6, 12, 3, ""), (7, 20, 3, ""), (8, 8, 2, ""), (9, 50, 2, ""),
+    (10, 12, 3, "t"), (11, 40, 2, "t"), (12, 10, 3, "ops"), (13, 30, 3, "ops"), (14, 20, 2, "ops")])
+def test_emitted_functions_match_graph(seed, n_terms, dim, extra):
     rng = np.random.default_rng(seed)
     g = rgb.Graph(dim)
-    D, x, k, om = _random_D(g, rng, n_terms, dim, with_t)
+    with_t = extra == "t"
+    D, x, k, om = _random_D(g, rng, n_terms, dim, with_t, rich=extra == "ops")
     ny = 2 * dim
     Dw = D.df(om)
     f_nodes = [-(D.df(ki)) / Dw for ki in k] + [D.df(xi) / Dw for xi in x]
