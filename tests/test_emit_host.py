@@ -541,3 +541,35 @@ def test_non_square_spline_matches_oracle(oracle):
     assert np.abs(jv - jvo).max() / np.abs(jvo).max() < 1e-12
     go = oracle.param_vjp_points(med, y, om, v)
     assert np.abs(grad - go).max() / np.abs(go).max() < 1e-12
+
+
+@pytest.mark.parametrize("cfg", ["cO2", "cX2"])
+def test_coldplasma_vjp_matches_graph(cfg):
+    """The cold-plasma determinant's VJP (second derivatives of eqs. 5-10;
+    the oracle's cold-plasma model is forward only): the emitted VJP, built
+    as host C++, against v^T J with J the graph's own symbolic derivatives
+    of f = (-D_k/D_w, D_x/D_w) on the unfactored graph, at points near the
+    benchmark's rays."""
+    from paper_2508_15967_amd import media
+    w = COLD[cfg]()
+    g, D, params = media.build(w.medium)
+    xs = [g.x(i) for i in range(3)]
+    ks = [g.k(i) for i in range(3)]
+    Dw = D.df(g.omega)
+    f_nodes = [-(D.df(ki)) / Dw for ki in ks] + [D.df(xi) / Dw for xi in xs]
+    J_nodes = [[fi.df(yj) for yj in xs + ks] for fi in f_nodes]
+    prog = g.compile(D, want_adjoint=True, compile_only=True)
+    rng = np.random.default_rng(21)
+    n = 64
+    y, om = _points(w, n, rng)
+    v = np.ascontiguousarray(rng.standard_normal((6, n)))
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, True, tmp)
+        jv, gp = np.zeros((6, n)), np.zeros(64)
+        lib.host_vjp(n, 6, C.c_void_p(y.ctypes.data), C.c_void_p(om.ctypes.data), _ptrs(params),
+                     C.c_void_p(v.ctypes.data), C.c_void_p(jv.ctypes.data), C.c_void_p(gp.ctypes.data))
+    jv_ref = np.zeros((6, n))
+    for r in range(n):
+        ev = lambda nd: g.eval(nd, list(y[:3, r]), list(y[3:, r]), float(om[r]))
+        jv_ref[:, r] = v[:, r] @ np.array([[ev(J_nodes[i][j]) for j in range(6)] for i in range(6)])
+    assert (np.abs(jv - jv_ref).max(axis=0) / np.abs(jv_ref).max(axis=0)).max() < 1e-11

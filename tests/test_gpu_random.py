@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 from paper_2508_15967_amd import raygraph as rgb
+from paper_2508_15967_amd import workloads as W
 from tests import gpu_util as U
 from tests.test_emit_host import _host_lib
 from tests.test_emit_random import _random_D
@@ -273,3 +274,86 @@ def test_random_relation_newton_matches_host(seed, n_terms, dim):
     assert np.array_equal(kg[1:], K[1:])  # the other components untouched
     fin = np.isfinite(Dg)
     assert float(mx.cpu()[0]) == (np.abs(Dg).max() if fin.all() else np.inf)
+
+
+def _host_rk4(lib, y0, om, t0, pp, steps, dt):
+    """Classic RK4 over the host build: end state and every stage state."""
+    Y = np.zeros((steps, 4) + y0.shape)
+    y, t = y0.copy(), t0.copy()
+    T = np.zeros((steps + 1,) + t0.shape)
+    T[0] = t0
+    for s in range(steps):
+        th = T[s] + 0.5 * dt
+        Y[s, 0] = y
+        k1 = _host_rhs(lib, y, om, T[s], pp)
+        Y[s, 1] = y + 0.5 * dt * k1
+        k2 = _host_rhs(lib, Y[s, 1], om, th, pp)
+        Y[s, 2] = y + 0.5 * dt * k2
+        k3 = _host_rhs(lib, Y[s, 2], om, th, pp)
+        Y[s, 3] = y + dt * k3
+        k4 = _host_rhs(lib, Y[s, 3], om, T[s] + dt, pp)
+        y = y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        T[s + 1] = T[s] + dt
+    return y, Y, T
+
+
+def _host_rk4_adjoint(lib, Y, T, om, pp, lam, dt):
+    """The discrete adjoint of _host_rk4's map, last step first."""
+    gp = np.zeros(64)
+    for s in range(Y.shape[0] - 1, -1, -1):
+        t, th = T[s], T[s] + 0.5 * dt
+        kb4 = dt / 6.0 * lam
+        yb4 = _host_vjp(lib, Y[s, 3], om, t + dt, pp, kb4, gp)
+        kb3 = dt / 3.0 * lam + dt * yb4
+        yb3 = _host_vjp(lib, Y[s, 2], om, th, pp, kb3, gp)
+        kb2 = dt / 3.0 * lam + 0.5 * dt * yb3
+        yb2 = _host_vjp(lib, Y[s, 1], om, th, pp, kb2, gp)
+        kb1 = dt / 6.0 * lam + 0.5 * dt * yb2
+        yb1 = _host_vjp(lib, Y[s, 0], om, t, pp, kb1, gp)
+        lam = lam + yb1 + yb2 + yb3 + yb4
+    return lam, gp
+
+
+@pytest.mark.parametrize("mode,x0", [("O", -5.0), ("X", 12.0)])
+def test_coldplasma_adjoint_matches_host_build(oracle, mode, x0):
+    """The adjoint of the cold-plasma medium (electrons and hydrogen ions,
+    oblique n_z = 0.2, k_x from the oracle's Newton solve; the oracle's
+    cold-plasma model is forward only): GPU endpoints and dL/dx0, dL/dk0
+    per ray against a host RK4 and discrete adjoint over the host build of
+    the emitted functions, whose VJP test_emit_host.py checks against the
+    graph's own second derivatives."""
+    from paper_2508_15967_amd import media
+    torch = U.torch_mod()
+    w = W.coldplasma(mode, n_rays=256, x0=x0, direction=1.0, dt=1e-2, n_steps=300, mu=W.MU_H, nz=W.CP_NZ)
+    print(f"[case] coldplasma adjoint {mode}", flush=True)
+    w.k0, _, _ = oracle.newton_k(w.medium, w.x0, w.k0, w.omega, component=w.solve_k, tol=1e-15, max_iter=60)
+    g, D, params = media.build(w.medium)
+    prog = g.compile(D, want_adjoint=True)
+    y0 = np.ascontiguousarray(np.concatenate([w.x0, w.k0]))
+    om, t0 = np.ascontiguousarray(w.omega), np.zeros(w.n)
+    target = w.x0 + np.random.default_rng(3).uniform(-1.0, 1.0, w.x0.shape)
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _host_lib(prog, True, tmp)
+        pp = (C.c_void_p * 8)(*([p.ctypes.data for p in params] + [None] * (8 - len(params))))
+        y, Y, T = _host_rk4(lib, y0, om, t0, pp, w.n_steps, w.dt)
+        yp, _, _ = _host_rk4(lib, np.nextafter(y0, np.inf), om, t0, pp, w.n_steps, w.dt)
+        ex, ek = U.ray_errors({"x": yp[:3], "k": yp[3:]}, {"x": y[:3], "k": y[3:]}, om, 3)
+        ok = np.maximum(ex, ek) <= 1e-12
+        assert (~ok).mean() <= U.MAX_ILL
+        lam0, _ = _host_rk4_adjoint(lib, Y, T, om, pp, np.concatenate([2.0 * (y[:3] - target), 0.5 * y[3:]]),
+                                    w.dt)
+    pt = [U.dev(p) for p in params]
+    x0d, k0d = U.dev(w.x0), U.dev(w.k0)
+    out = prog.trace(x0d, k0d, U.dev(om), pt, dt=w.dt, n_steps=w.n_steps, checkpoint_every=100)
+    torch.cuda.synchronize()
+    ex, ek = U.ray_errors({"x": out["x"].cpu().numpy(), "k": out["k"].cpu().numpy()},
+                          {"x": y[:3], "k": y[3:]}, om, 3)
+    assert ex[ok].max() < U.TOL and ek[ok].max() < U.TOL, (ex[ok].max(), ek[ok].max())
+    lx = (2.0 * (out["x"] - U.dev(target))).contiguous()
+    lk = (0.5 * out["k"]).contiguous()
+    gx0, gk0 = torch.empty_like(x0d), torch.empty_like(k0d)
+    prog.adjoint_desc(out["_desc"], lx, lk, gx0, gk0, [torch.empty_like(p) for p in pt])
+    torch.cuda.synchronize()
+    rel = lambda a, b: np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+    assert rel(gx0.cpu().numpy(), lam0[:3])[ok].max() < 1e-9
+    assert rel(gk0.cpu().numpy(), lam0[3:])[ok].max() < 1e-9
